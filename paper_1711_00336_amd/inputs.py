@@ -1,0 +1,376 @@
+"""Seeded synthetic inputs for the coupled LBM-DEM time step.
+
+This module is shared by the FP64 CPU oracle (tests) and by the GPU library.
+It holds none of the method's arithmetic: only a counter-based random number
+generator, geometric placement of non-overlapping spheres, and parameter
+presets for the workloads of the paper's Sec. 4 (hindered settling in a
+periodic box, Sec. 4.1 "Setup") and Sec. 5 (walls), scaled to lattice units.
+
+Random numbers come from SplitMix64 (Steele, Lea and Flood, "Fast splittable
+pseudorandom number generators", OOPSLA 2014), evaluated as a counter-based
+generator: output k of stream s for seed S is mix64(S*phi + s*psi + (k+1)*phi),
+so every draw is addressable without sequential state.
+
+Conventions used by every consumer (documented, not shared code):
+  * cell (i, j, k) has its centre at (i+1/2, j+1/2, k+1/2); flat index
+    c = i + nx*(j + ny*k) (x fastest);
+  * walls, on non-periodic axes, are the planes 0 and n of that axis;
+  * PDF deviations df[q, c] = f_q - w_q (rest state: all zero);
+  * particle vectors are (N, 3) float64 arrays, scalars (N,) arrays.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, asdict
+from typing import Optional
+
+import numpy as np
+
+_M64 = (1 << 64) - 1
+_PHI = 0x9E3779B97F4A7C15
+_PSI = 0xD1B54A32D192ED03
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    z = z.astype(np.uint64, copy=True)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def splitmix64(seed: int, stream: int, counters: np.ndarray) -> np.ndarray:
+    """Counter-based SplitMix64 outputs (uint64) for the given counters."""
+    base = (int(seed) * _PHI + int(stream) * _PSI) & _M64
+    c = np.asarray(counters, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(base) + (c + np.uint64(1)) * np.uint64(_PHI)
+    return _mix64(z)
+
+
+def uniform(seed: int, stream: int, start: int, n: int) -> np.ndarray:
+    """n doubles in [0, 1) from stream `stream`, counters start..start+n-1."""
+    k = np.arange(start, start + n, dtype=np.uint64)
+    return (splitmix64(seed, stream, k) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+# streams
+_S_DIAM, _S_POS, _S_RHO, _S_DOMAIN, _S_PERTURB = 1, 2, 3, 4, 5
+
+
+# ---------------------------------------------------------------------------
+# parameters
+# ---------------------------------------------------------------------------
+@dataclass
+class Params:
+    """Physical and numerical parameters of one domain, in lattice units
+    (dx = dt = 1, c_s^2 = 1/3, rho_f = 1)."""
+    n: tuple = (32, 32, 64)
+    periodic: tuple = (1, 1, 0)
+    tau: float = 0.8
+    rho_f: float = 1.0
+    gravity: tuple = (0.0, 0.0, -1e-5)      # acceleration acting on particles
+    body_force: tuple = (0.0, 0.0, 0.0)     # fluid body-force density f_b
+    body_force_auto: int = 0                # 1: f_b balances the particles' net weight
+    e_n: float = 0.88
+    mu_c: float = 0.25
+    T_c: float = 0.0                        # <= 0: 20 DEM substeps
+    h_c: float = 0.5
+    h_min: float = 1e-5
+    lub_stab: int = 1                       # explicit-stability floor on the gap
+    n_int: int = 10
+    n_dem: int = 1
+    c_am: float = 0.5
+    use_lub: int = 1
+    use_am: int = 1
+    precision: str = "fp64"                 # "fp64" | "fp32dev"
+
+    def copy(self, **kw) -> "Params":
+        d = asdict(self)
+        d.update(kw)
+        return Params(**d)
+
+
+@dataclass
+class Particles:
+    x: np.ndarray
+    u: np.ndarray
+    w: np.ndarray
+    d: np.ndarray
+    rho_p: np.ndarray
+    a: np.ndarray = None
+
+    def __post_init__(self):
+        n = len(self.d)
+        if self.a is None:
+            self.a = np.zeros((n, 3))
+        for k in ("x", "u", "w", "a"):
+            setattr(self, k, np.ascontiguousarray(getattr(self, k), dtype=np.float64).reshape(n, 3))
+        self.d = np.ascontiguousarray(self.d, dtype=np.float64).reshape(n)
+        self.rho_p = np.ascontiguousarray(self.rho_p, dtype=np.float64).reshape(n)
+
+    @property
+    def n(self) -> int:
+        return len(self.d)
+
+    def copy(self) -> "Particles":
+        return Particles(self.x.copy(), self.u.copy(), self.w.copy(), self.d.copy(),
+                         self.rho_p.copy(), self.a.copy())
+
+
+@dataclass
+class Case:
+    """A synthetic workload: parameters plus an initial particle set."""
+    name: str
+    params: Params
+    particles: Particles
+    seed: int
+    note: str = ""
+
+
+# ---------------------------------------------------------------------------
+# sphere placement
+# ---------------------------------------------------------------------------
+def _draw_positions(seed, stream_base, counter, n, box, periodic, radii):
+    """Uniform positions; on walled axes the sphere must lie inside [r, L-r]."""
+    out = np.empty((n, 3))
+    for a in range(3):
+        u = uniform(seed, _S_POS * 16 + a + stream_base, counter, n)
+        L = float(box[a])
+        if periodic[a]:
+            out[:, a] = u * L
+        else:
+            out[:, a] = radii + u * (L - 2.0 * radii)
+    return out
+
+
+class _Grid:
+    """Uniform hashing grid over the sphere centres (cell edge >= cell)."""
+
+    def __init__(self, pos, box, periodic, cell):
+        self.box, self.periodic = box, periodic
+        self.nc = [max(1, int(box[a] // cell)) for a in range(3)]
+        self.csz = [box[a] / self.nc[a] for a in range(3)]
+        self.pos = pos
+        ci = self.cells(pos)
+        key = ci[:, 0] + self.nc[0] * (ci[:, 1] + self.nc[1] * ci[:, 2])
+        self.order = np.argsort(key, kind="stable")
+        ntot = self.nc[0] * self.nc[1] * self.nc[2]
+        cnt = np.bincount(key, minlength=ntot)
+        self.start = np.zeros(ntot + 1, np.int64)
+        np.cumsum(cnt, out=self.start[1:])
+
+    def cells(self, p):
+        return np.stack([np.clip((p[:, a] / self.csz[a]).astype(np.int64), 0, self.nc[a] - 1)
+                         for a in range(3)], 1)
+
+    def pairs(self, query, cutoff):
+        """Pairs (i in query, j != i) with minimum-image distance < cutoff(i, j)."""
+        pos, box, periodic, nc = self.pos, self.box, self.periodic, self.nc
+        q = np.asarray(query, np.int64)
+        ci = self.cells(pos[q])
+        I, J = [], []
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    nb = ci + np.array([dx, dy, dz])
+                    valid = np.ones(len(q), bool)
+                    for a in range(3):
+                        if periodic[a]:
+                            nb[:, a] %= nc[a]
+                        else:
+                            valid &= (nb[:, a] >= 0) & (nb[:, a] < nc[a])
+                    nb = np.where(valid[:, None], nb, 0)
+                    nk = nb[:, 0] + nc[0] * (nb[:, 1] + nc[1] * nb[:, 2])
+                    s, e = self.start[nk], self.start[nk + 1]
+                    cnt = np.where(valid, e - s, 0)
+                    tot = int(cnt.sum())
+                    if tot == 0:
+                        continue
+                    ii = np.repeat(q, cnt)
+                    within = np.arange(tot) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+                    jj = self.order[np.repeat(s, cnt) + within]
+                    m = jj != ii
+                    I.append(ii[m]); J.append(jj[m])
+        if not I:
+            return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 3))
+        I = np.concatenate(I); J = np.concatenate(J)
+        n = len(pos)
+        # a pair can be found twice when a periodic axis has fewer than 3 cells
+        pk = np.unique(I * n + J)
+        I, J = pk // n, pk % n
+        dv = pos[J] - pos[I]
+        for a in range(3):
+            if periodic[a]:
+                dv[:, a] -= box[a] * np.round(dv[:, a] / box[a])
+        dist = np.sqrt((dv * dv).sum(1))
+        m = dist < cutoff(I, J)
+        return I[m], J[m], dv[m]
+
+
+def _neighbour_pairs(pos, box, periodic, cell, cutoff):
+    """All pairs (i<j) with minimum-image distance < cutoff(i, j)."""
+    g = _Grid(pos, box, periodic, cell)
+    I, J, dv = g.pairs(np.arange(len(pos)), cutoff)
+    m = I < J
+    return I[m], J[m], dv[m]
+
+
+def place_spheres(seed, box, periodic, diam, max_rounds=400, relax_tol=1e-3):
+    """Non-overlapping uniform random spheres.
+
+    First a parallel random sequential addition: particle i is redrawn while
+    it overlaps any particle j < i. If that stalls (dense packings beyond the
+    RSA limit), the remaining overlaps are removed by a geometric relaxation
+    that pushes overlapping pairs apart (no physics: equal and opposite
+    displacements of half the overlap), until the largest overlap is below
+    relax_tol * d_min. The paper prepares dense packings the same way: random
+    placement followed by overlap removal (Sec. 4.1, Setup).
+    """
+    diam = np.asarray(diam, np.float64)
+    n = len(diam)
+    box = [float(b) for b in box]
+    if n == 0:
+        return np.zeros((0, 3))
+    r = 0.5 * diam
+    dmax = float(diam.max())
+    pos = _draw_positions(seed, 0, 0, n, box, periodic, r)
+    counter = n
+    cut = lambda I, J: r[I] + r[J]
+    query = np.arange(n)
+    for rnd in range(max_rounds):
+        g = _Grid(pos, box, periodic, dmax)
+        I, J, _dv = g.pairs(query, cut)
+        if len(I) == 0:
+            return pos
+        bad = np.unique(np.maximum(I, J))  # redraw the later one of each pair
+        if len(bad) > 0.5 * n and rnd > 20:
+            break
+        newp = _draw_positions(seed, 0, counter, len(bad), box, periodic, r[bad])
+        counter += len(bad)
+        pos[bad] = newp
+        query = bad
+    # geometric relaxation
+    for it in range(20000):
+        I, J, dv = _neighbour_pairs(pos, box, periodic, dmax, cut)
+        if len(I) == 0:
+            return pos
+        dist = np.sqrt((dv * dv).sum(1))
+        ov = r[I] + r[J] - dist
+        if ov.max() < relax_tol * diam.min():
+            return pos
+        nrm = dv / np.maximum(dist, 1e-12)[:, None]
+        push = (0.5 * ov + 1e-4 * diam.min())[:, None] * nrm
+        disp = np.zeros_like(pos)
+        np.add.at(disp, I, -push)
+        np.add.at(disp, J, push)
+        pos += disp
+        for a in range(3):
+            if periodic[a]:
+                pos[:, a] %= box[a]
+            else:
+                pos[:, a] = np.clip(pos[:, a], r, box[a] - r)
+    raise RuntimeError("sphere placement did not converge")
+
+
+def count_for_fraction(eps_p: float, ncells: int, d_mean: float) -> int:
+    """Number of monodisperse spheres giving solid fraction eps_p."""
+    return int(round(eps_p * ncells / (math.pi / 6.0 * d_mean ** 3)))
+
+
+def draw_diameters(seed, n_or_eps, ncells, d_lo, d_hi):
+    """Diameters uniform in [d_lo, d_hi]. If n_or_eps is a float < 1 it is a
+    target solid fraction: spheres are added until their volume reaches it."""
+    if isinstance(n_or_eps, float) and n_or_eps < 1.0:
+        target = n_or_eps * ncells
+        est = int(target / (math.pi / 6.0 * ((d_lo + d_hi) / 2) ** 3) * 1.3) + 16
+        u = uniform(seed, _S_DIAM, 0, est)
+        d = d_lo + (d_hi - d_lo) * u
+        v = np.cumsum(math.pi / 6.0 * d ** 3)
+        n = int(np.searchsorted(v, target)) + 1
+        n = min(n, est)
+        # pick n or n-1, whichever is closer
+        if n > 1 and abs(v[n - 2] - target) < abs(v[n - 1] - target):
+            n -= 1
+        return d[:n].copy()
+    n = int(n_or_eps)
+    if d_lo == d_hi:
+        return np.full(n, float(d_lo))
+    return d_lo + (d_hi - d_lo) * uniform(seed, _S_DIAM, 0, n)
+
+
+def make_particles(seed, params: Params, n_or_eps, d_lo, d_hi, rho_ratio):
+    nc = params.n[0] * params.n[1] * params.n[2]
+    d = draw_diameters(seed, n_or_eps, nc, d_lo, d_hi)
+    pos = place_spheres(seed, params.n, params.periodic, d)
+    n = len(d)
+    rp = np.full(n, float(rho_ratio) * params.rho_f)
+    return Particles(pos, np.zeros((n, 3)), np.zeros((n, 3)), d, rp)
+
+
+# ---------------------------------------------------------------------------
+# workload presets (lattice units)
+# ---------------------------------------------------------------------------
+def case_small_walled(seed=0, n=(32, 32, 64), n_particles=64):
+    """32x32x64 cells, periodic x/y, no-slip walls at z=0 and z=64; 64 spheres
+    d=0.5, density ratio 2.5, rest start; gravity 1e-5 along -z; tau=0.8;
+    n_int=10 interaction subcycles with 1 DEM substep each (FP64)."""
+    p = Params(n=tuple(n), periodic=(1, 1, 0), tau=0.8, gravity=(0.0, 0.0, -1e-5),
+               body_force=(0.0, 0.0, 0.0), body_force_auto=0, e_n=0.88, mu_c=0.25,
+               T_c=0.0, h_c=0.5, n_int=10, n_dem=1, precision="fp64")
+    parts = make_particles(seed, p, n_particles, 0.5, 0.5, 2.5)
+    return Case("walled-32x32x64-64sph", p, parts, seed)
+
+
+def case_dilute_periodic(seed=0, n=128, eps_p=0.05, d=0.8, precision="fp32dev"):
+    """n^3 fully periodic cells, spheres d=0.8 at solid fraction 0.05, density
+    ratio 2.5, gravity 1e-5 (-z) on the particles, a balancing fluid body force
+    (Sec. 4.1 Setup); tau=0.7; n_int=10, n_dem=1."""
+    p = Params(n=(n, n, n), periodic=(1, 1, 1), tau=0.7, gravity=(0.0, 0.0, -1e-5),
+               body_force_auto=1, e_n=0.88, mu_c=0.25, T_c=0.0, h_c=d,
+               n_int=10, n_dem=1, precision=precision)
+    nc = n ** 3
+    npart = count_for_fraction(eps_p, nc, d)
+    parts = make_particles(seed, p, npart, d, d, 2.5)
+    return Case(f"periodic-{n}^3-eps{eps_p}", p, parts, seed)
+
+
+def case_dense_walled(seed=0, n=(256, 256, 512), eps_p=0.4, precision="fp32dev",
+                      n_dem=10, n_int=10):
+    """Dense suspension: walls in z, d ~ U[0.9, 1.1], solid fraction 0.4,
+    density ratio 2.5, restitution 0.9, lubrication with cut-off 1.0."""
+    p = Params(n=tuple(n), periodic=(1, 1, 0), tau=0.7, gravity=(0.0, 0.0, -1e-5),
+               body_force_auto=0, e_n=0.9, mu_c=0.25, T_c=0.0, h_c=1.0,
+               n_int=n_int, n_dem=n_dem, precision=precision)
+    parts = make_particles(seed, p, float(eps_p), 0.9, 1.1, 2.5)
+    return Case(f"dense-{n[0]}x{n[1]}x{n[2]}-eps{eps_p}", p, parts, seed)
+
+
+def batch_domain_draw(seed, i, edge_lo=16, edge_hi=96):
+    """Draw domain i of a batched sweep: cubic edge log-uniform in
+    [edge_lo, edge_hi], solid fraction U[0.01, 0.5], diameter U[0.6, 1.0],
+    density ratio U[1.5, 4]."""
+    u = uniform(seed, _S_DOMAIN, 4 * i, 4)
+    edge = int(math.floor(math.exp(math.log(edge_lo) + u[0] * (math.log(edge_hi) - math.log(edge_lo)))))
+    edge = min(max(edge, edge_lo), edge_hi)
+    eps = 0.01 + 0.49 * u[1]
+    d = 0.6 + 0.4 * u[2]
+    rr = 1.5 + 2.5 * u[3]
+    return edge, eps, d, rr
+
+
+def case_settling(seed, edge, eps_p, d, rho_ratio, precision="fp32dev", n_int=10):
+    p = Params(n=(edge, edge, edge), periodic=(1, 1, 1), tau=0.7, gravity=(0.0, 0.0, -1e-5),
+               body_force_auto=1, e_n=0.88, mu_c=0.25, T_c=0.0, h_c=d,
+               n_int=n_int, n_dem=1, precision=precision)
+    npart = count_for_fraction(eps_p, edge ** 3, d)
+    parts = make_particles(seed, p, npart, d, d, rho_ratio)
+    return Case(f"settling-{edge}^3-eps{eps_p:.3f}", p, parts, seed)
+
+
+def perturbed_state(seed, ncells, amp=1e-6, n_fields=19):
+    """Random PDF deviations of amplitude amp (for parity tests of the
+    stream-collide away from rest). Zero-mean per cell is not enforced."""
+    u = uniform(seed, _S_PERTURB, 0, n_fields * ncells).reshape(n_fields, ncells)
+    return amp * (2.0 * u - 1.0)
