@@ -1,0 +1,193 @@
+/*
+ * lbdem.h -- C ABI of the MI355X (gfx950) library for one coupled lattice
+ * Boltzmann / discrete element time step of the unresolved particle method
+ * of Rettinger & Ruede, arXiv 1711.00336 (Alg. 1, Sec. 3.3).
+ *
+ * Units: lattice units throughout (Sec. 3.2.2, last paragraph): dx = dt = 1,
+ * c_s^2 = 1/3, fluid density rho_f = 1. Cell (i,j,k) has its centre at
+ * (i+1/2, j+1/2, k+1/2); flat cell index c = i + nx*(j + ny*k). On an axis
+ * that is not periodic the domain is bounded by no-slip walls at the planes
+ * 0 and n of that axis. PDFs are exchanged as deviations f_q - w_q from the
+ * rest state, in the D3Q19 order 0 rest; 1..6 = +x,-x,+y,-y,+z,-z;
+ * 7..18 = (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),
+ * (-1,0,1),(0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1).
+ *
+ * Ownership: the library owns all device memory of a domain. Host arrays
+ * passed in are read (or written) synchronously during the call and stay
+ * owned by the caller. A domain handle is not thread-safe; separate handles
+ * may be used from separate threads and streams.
+ *
+ * Errors: every call returns an lbdem_status; nothing throws across the ABI.
+ * lbdem_last_error() returns a message for the last failure of a handle
+ * (or of the calling thread when the handle is NULL). After LBDEM_E_DEVICE
+ * the handle should be destroyed.
+ */
+#ifndef LBDEM_H
+#define LBDEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBDEM_OK = 0,
+    LBDEM_E_INVALID = 1,   /* bad argument, out-of-domain particle, size mismatch */
+    LBDEM_E_OOM = 2,       /* device allocation failed */
+    LBDEM_E_UNSTABLE = 3,  /* non-finite state, eps_f <= 0, particle through a wall,
+                              or a particle moved further than the search skin in
+                              one interaction subcycle */
+    LBDEM_E_DEVICE = 4,    /* HIP runtime error */
+    LBDEM_E_BUSY = 5,      /* serving: result not ready / no capacity */
+    LBDEM_E_STATE = 6      /* call not valid in the handle's current state */
+} lbdem_status;
+
+enum { LBDEM_FP64 = 0, LBDEM_FP32_DEV = 1 };   /* cell-field precision */
+enum { LBDEM_MEM_HOST = 0, LBDEM_MEM_DEVICE = 1 };
+
+/* Fields readable with lbdem_read_field (FP64 output, [ncomp][Nc]). */
+enum {
+    LBDEM_FIELD_DRHO = 0,   /* rho - 1 of the current post-stream state (1 comp) */
+    LBDEM_FIELD_J = 1,      /* sum_q c_q f_q at the last step's start (3 comps) */
+    LBDEM_FIELD_EPS_F = 2,  /* fluid volume fraction of the current positions (1) */
+    LBDEM_FIELD_F_ACC = 3,  /* subcycle-mean force density of the last step (3) */
+    LBDEM_FIELD_DUDT = 4,   /* Du_f/Dt of the last step (3) */
+    LBDEM_FIELD_GRADP = 5,  /* grad P of the last step (3) */
+    LBDEM_FIELD_UPREV = 6,  /* fluid-phase velocity kept for the next time derivative (3) */
+    LBDEM_FIELD_PDF = 7     /* f_q - w_q of the current state (19) */
+};
+
+/* Problem statement (Sec. 3.1, 3.2; Sec. 4.1 and 5.1 setups). */
+typedef struct lbdem_params {
+    int32_t n[3];            /* cells per axis (>= 1) */
+    int32_t periodic[3];     /* 1 periodic, 0 no-slip walls at 0 and n */
+    double tau;              /* BGK relaxation time, > 1/2 (Eq. visc_tau) */
+    double rho_f;            /* fluid density in the closures (1) */
+    double gravity[3];       /* g, acting on the particles (Sec. 4.1) */
+    double body_force[3];    /* fluid body-force density f_b (Eq. GNS) */
+    int32_t body_force_auto; /* 1: fully periodic domains get
+                                f_b = -sum_p (rho_p - rho_f) V_p g / (nx ny nz),
+                                walled domains f_b = 0 (Sec. 4.1 Setup) */
+    double e_n;              /* dry coefficient of restitution (Eq. damping_to_stiffness) */
+    double mu_c;             /* Coulomb friction coefficient (Sec. 3.1.1) */
+    double T_c;              /* collision time; <= 0 selects 20 DEM substeps (Eq. collision_time) */
+    double h_c;              /* lubrication cut-off gap (Sec. 3.1.3) */
+    double h_min;            /* lower gap limit, 1e-5 (Sec. 3.1.3) */
+    int32_t lub_stab;        /* 1: also floor the gap where the explicit squeeze
+                                force would overshoot: 3 pi mu <d>^2 dt_DEM / (8 m_ij) */
+    int32_t use_lub;         /* lubrication on/off */
+    int32_t use_am;          /* added mass on/off */
+    int32_t n_int;           /* interaction subcycles per LBM step (Alg. 1) */
+    int32_t n_dem;           /* DEM substeps per interaction subcycle (Alg. 1) */
+    double c_am;             /* added-mass coefficient, 0.5 (Table 1) */
+    int32_t precision;       /* LBDEM_FP64 or LBDEM_FP32_DEV (PDFs and cell fields
+                                as FP32 deviations from the rest weights; particle
+                                integration and reductions stay FP64) */
+    uint32_t flags;          /* reserved, 0 */
+} lbdem_params;
+
+typedef struct lbdem_diag {
+    double mass_dev;         /* sum_x (rho - 1) */
+    double mom_fluid[3];     /* sum_x sum_q c_q f_q */
+    double mom_part[3];      /* sum_p m_p u_p */
+    double u_ps;             /* mean_p u_p,z - mean_x u_f,z (Sec. 4.1, relative settling velocity) */
+    double mean_eps_f;
+    double min_eps_f;
+    double max_u;            /* max_x |u_bar| */
+    int64_t step;
+    int64_t np;
+} lbdem_diag;
+
+/* Full state as host arrays (checkpoint, parity injection). */
+typedef struct lbdem_state_view {
+    double *df;              /* [19][Nc] f_q - w_q, post-stream */
+    double *uprev;           /* [3][Nc] fluid-phase velocity of the previous step */
+    int64_t step;            /* steps taken (0: no time derivative yet) */
+    int64_t np;              /* particle count (in: capacity of the arrays on get) */
+    double *x, *u, *omega, *accel;  /* [np][3] */
+    double *d, *rho_p;       /* [np] */
+} lbdem_state_view;
+
+typedef struct lbdem_domain *lbdem_domain_t;
+
+/* Message of the last failure on h (NULL: of the calling thread). Never NULL. */
+const char *lbdem_last_error(lbdem_domain_t h);
+
+/* Paper defaults: rho_f=1, e_n=0.88, mu_c=0.25 (Sec. 4.1), h_min=1e-5
+ * (Sec. 3.1.3), c_am=0.5 (Table 1), n_int=10 (Sec. 4.1), n_dem=1, T_c auto,
+ * h_c=0.5, lubrication and added mass on, FP64, 32x32x32 periodic, tau=0.8. */
+lbdem_status lbdem_params_default(lbdem_params *p);
+
+/* Route device allocations through a caller allocator (e.g. a framework's
+ * caching allocator). alloc returns device memory of `bytes` or NULL; free
+ * releases it. Pass NULLs to restore hipMalloc/hipFree. Applies to domains
+ * created afterwards. */
+lbdem_status lbdem_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                                 void (*free_fn)(void *ptr, void *ctx), void *ctx);
+
+/* Create a domain at rest (all f_q = w_q, no particles) on the current HIP
+ * device. hip_stream is a hipStream_t (NULL: the library creates one).
+ * E_INVALID if tau <= 1/2, a size < 1, n_int or n_dem < 1. */
+lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_t *out);
+
+/* Free everything; NULL is a no-op. */
+lbdem_status lbdem_destroy(lbdem_domain_t h);
+
+/* Append n spheres (Sec. 3.1): host arrays x,u,omega [n][3], d,rho_p [n].
+ * Copied synchronously; the fluid volume fraction (Eq. fluid_volume_fraction)
+ * and an automatic f_b are recomputed. E_INVALID if a centre lies outside
+ * the domain, a sphere crosses a wall, d <= 0 or rho_p <= 0. */
+lbdem_status lbdem_add_particles(lbdem_domain_t h, int64_t n, const double *x, const double *u,
+                                 const double *omega, const double *d, const double *rho_p);
+
+/* Enqueue nsteps coupled time steps (Alg. 1) on the domain's stream.
+ * Asynchronous: errors detected on the device surface at lbdem_sync. */
+lbdem_status lbdem_step(lbdem_domain_t h, int64_t nsteps);
+
+/* Wait for the stream; returns E_UNSTABLE if any step flagged instability. */
+lbdem_status lbdem_sync(lbdem_domain_t h);
+
+/* Copy one field (FP64, [ncomp][Nc]) to host or device memory `out`
+ * (caller-owned, ncomp*Nc doubles). Synchronous. */
+lbdem_status lbdem_read_field(lbdem_domain_t h, int field, int mem_kind, double *out);
+
+/* Particle data in insertion order: x, u, omega, accel [np][3] (NULL skips). */
+lbdem_status lbdem_read_particles(lbdem_domain_t h, int mem_kind, double *x, double *u,
+                                  double *omega, double *accel);
+
+/* Fluid-particle forces of the last subcycle [np][3] (NULL skips):
+ * added mass, drag, pressure gradient, and their sum with gravity+buoyancy. */
+lbdem_status lbdem_read_particle_forces(lbdem_domain_t h, double *F_am, double *F_d,
+                                        double *F_pr, double *F_const);
+
+/* FP64 reductions of the current state (Sec. 4.1 settling velocity). */
+lbdem_status lbdem_diagnostics(lbdem_domain_t h, lbdem_diag *out);
+
+int64_t lbdem_num_cells(lbdem_domain_t h);
+int64_t lbdem_num_particles(lbdem_domain_t h);
+
+/* Whole state as host arrays. get: v->np is the capacity of the particle
+ * arrays and returns the count (E_INVALID if too small). set: replaces the
+ * PDFs, u_prev, step and all particles. */
+lbdem_status lbdem_get_state(lbdem_domain_t h, lbdem_state_view *v);
+lbdem_status lbdem_set_state(lbdem_domain_t h, const lbdem_state_view *v);
+
+/* Checkpoint as one opaque host blob. save with blob == NULL returns the
+ * size in *size; otherwise *size must be >= the size. load validates the
+ * blob against the domain's shape. */
+lbdem_status lbdem_save_state(lbdem_domain_t h, void *blob, size_t *size);
+lbdem_status lbdem_load_state(lbdem_domain_t h, const void *blob, size_t size);
+
+/* Launch-configuration query for benchmarks: average device time in ms of
+ * the named kernel class over the last lbdem_step call when timing is on
+ * (lbdem_set_timing). Classes: 0 stream-collide, 1 moments, 2 cell fields,
+ * 3 particle passes, 4 gathers, 5 DEM, 6 binning. */
+lbdem_status lbdem_set_timing(lbdem_domain_t h, int on);
+lbdem_status lbdem_kernel_time(lbdem_domain_t h, int cls, double *ms_total, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBDEM_H */

@@ -1,0 +1,904 @@
+// Host runtime and C ABI of the coupled LBM-DEM library (include/lbdem.h).
+// One domain = one set of device arrays on one HIP stream; a step is the
+// kernel sequence of Alg. 1 (Rettinger & Ruede, Sec. 3.3), optionally
+// captured once into a HIP graph and replayed.
+#include "../../include/lbdem.h"
+#include "lbdem_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lbdem;
+
+namespace {
+
+thread_local std::string g_thread_err = "";
+
+void *(*g_alloc)(size_t, void *) = nullptr;
+void (*g_free)(void *, void *) = nullptr;
+void *g_alloc_ctx = nullptr;
+
+struct DevAlloc {
+    void *(*alloc)(size_t, void *);
+    void (*free_fn)(void *, void *);
+    void *ctx;
+};
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+};
+
+inline void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) throw HipError{e, what};
+}
+
+struct Oom {
+    size_t bytes;
+};
+
+}  // namespace
+
+struct lbdem_domain {
+    lbdem_params prm;
+    DevAlloc al{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int prec = LBDEM_FP64;
+    Geo geo{};
+    Phys phys{};
+    std::string err;
+    int64_t step_host = 0;
+
+    // cell arrays (one of the two precisions is used)
+    void *df[2] = {nullptr, nullptr};
+    int cur = 0;
+    void *drho = nullptr, *j = nullptr, *uprev = nullptr, *dudt = nullptr, *gradp = nullptr;
+    void *epsp = nullptr, *fam = nullptr, *facc = nullptr;
+    // bins
+    int *cnt = nullptr, *start = nullptr, *list = nullptr, *bsum = nullptr;
+    int64_t list_cap = 0;
+    // particles
+    Parts pt{};
+    double dmax = 0.0;
+    // misc
+    int *flags = nullptr;
+    long long *stepc = nullptr;
+    double *diag_part = nullptr, *diag_out = nullptr, *tmp = nullptr;
+    int64_t tmp_len = 0;
+    std::vector<void *> owned;
+
+    // timing
+    bool timing = false;
+    struct Ev {
+        hipEvent_t a, b;
+        int cls;
+    };
+    std::vector<Ev> ev_pool;
+    size_t ev_used = 0;
+    double cls_ms[8] = {0};
+    int64_t cls_n[8] = {0};
+
+    size_t rsize() const { return prec == LBDEM_FP64 ? sizeof(double) : sizeof(float); }
+
+    void *dalloc(size_t bytes)
+    {
+        if (bytes == 0) bytes = 256;
+        void *p = nullptr;
+        if (al.alloc) {
+            p = al.alloc(bytes, al.ctx);
+            if (!p) throw Oom{bytes};
+        } else {
+            hipError_t e = hipMalloc(&p, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                throw Oom{bytes};
+            }
+        }
+        owned.push_back(p);
+        return p;
+    }
+    void dfree(void *p)
+    {
+        if (!p) return;
+        auto it = std::find(owned.begin(), owned.end(), p);
+        if (it != owned.end()) owned.erase(it);
+        if (al.free_fn) al.free_fn(p, al.ctx);
+        else (void)hipFree(p);
+    }
+
+    Desc desc() const
+    {
+        Desc D{};
+        D.g = geo;
+        D.p = phys;
+        D.b = Bins{cnt, start, list, bsum};
+        D.pt = pt;
+        D.flags = flags;
+        D.stepc = stepc;
+        return D;
+    }
+
+    template <typename R>
+    Cells<R> cells() const
+    {
+        Cells<R> C{};
+        C.df_src = (R *)df[cur];
+        C.df_dst = (R *)df[cur ^ 1];
+        C.drho = (R *)drho;
+        C.j = (R *)j;
+        C.uprev = (R *)uprev;
+        C.dudt = (R *)dudt;
+        C.gradp = (R *)gradp;
+        C.epsp = (R *)epsp;
+        C.fam = (R *)fam;
+        C.facc = (R *)facc;
+        return C;
+    }
+
+    double *scratch(int64_t n)
+    {
+        if (n > tmp_len) {
+            dfree(tmp);
+            tmp = (double *)dalloc(sizeof(double) * (size_t)n);
+            tmp_len = n;
+        }
+        return tmp;
+    }
+
+    void ev_begin(int cls, hipEvent_t &b_out)
+    {
+        if (ev_used == ev_pool.size()) {
+            Ev e{};
+            hip_check(hipEventCreate(&e.a), "hipEventCreate");
+            hip_check(hipEventCreate(&e.b), "hipEventCreate");
+            ev_pool.push_back(e);
+        }
+        Ev &e = ev_pool[ev_used++];
+        e.cls = cls;
+        hip_check(hipEventRecord(e.a, stream), "hipEventRecord");
+        b_out = e.b;
+    }
+};
+
+namespace {
+
+lbdem_status fail(lbdem_domain_t h, lbdem_status st, const std::string &msg)
+{
+    if (h) h->err = msg;
+    else g_thread_err = msg;
+    return st;
+}
+
+template <typename F>
+lbdem_status guarded(lbdem_domain_t h, F &&f)
+{
+    try {
+        return f();
+    } catch (const HipError &e) {
+        return fail(h, LBDEM_E_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const Oom &o) {
+        return fail(h, LBDEM_E_OOM, "device allocation of " + std::to_string(o.bytes) + " bytes failed");
+    } catch (const std::exception &e) {
+        return fail(h, LBDEM_E_INVALID, e.what());
+    }
+}
+
+// timed launch of one kernel class
+template <typename F>
+void launch_cls(lbdem_domain_t h, int cls, F &&f)
+{
+    if (!h->timing) {
+        f();
+        return;
+    }
+    hipEvent_t b;
+    h->ev_begin(cls, b);
+    f();
+    hip_check(hipEventRecord(b, h->stream), "hipEventRecord");
+}
+
+void harvest_timing(lbdem_domain_t h)
+{
+    for (size_t i = 0; i < h->ev_used; ++i) {
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, h->ev_pool[i].a, h->ev_pool[i].b), "hipEventElapsedTime");
+        h->cls_ms[h->ev_pool[i].cls] += ms;
+        h->cls_n[h->ev_pool[i].cls] += 1;
+    }
+    h->ev_used = 0;
+}
+
+void resolve_phys(lbdem_domain_t h)
+{
+    const lbdem_params &p = h->prm;
+    Phys &P = h->phys;
+    P.tau = p.tau;
+    P.omega = 1.0 / p.tau;
+    P.rho_f = p.rho_f;
+    P.mu = p.rho_f * (p.tau - 0.5) / 3.0;  // Eq. visc_tau with tau_e = tau
+    for (int a = 0; a < 3; ++a) {
+        P.g[a] = p.gravity[a];
+        P.fb[a] = p.body_force[a];
+    }
+    P.e_n = p.e_n;
+    P.mu_c = p.mu_c;
+    P.h_c = p.h_c;
+    P.h_min = p.h_min;
+    P.lub_stab = p.lub_stab;
+    P.use_lub = p.use_lub;
+    P.use_am = p.use_am;
+    P.n_int = p.n_int;
+    P.n_dem = p.n_dem;
+    P.dt_int = 1.0 / p.n_int;
+    P.dt_dem = P.dt_int / p.n_dem;
+    P.T_c = p.T_c > 0.0 ? p.T_c : 20.0 * P.dt_dem;
+    P.c_am = p.c_am;
+    P.skin = 0.1;
+    P.rbin = 1;
+}
+
+void update_search(lbdem_domain_t h)
+{
+    Phys &P = h->phys;
+    const double reach = h->dmax + (P.use_lub ? std::max(P.h_c, 0.0) : 0.0) + 2.0 * P.skin;
+    P.rbin = std::max(1, (int)std::ceil(reach));
+    if (P.rbin > 8) throw std::runtime_error("interaction reach d_max + h_c exceeds the 8-cell search limit");
+}
+
+void update_body_force(lbdem_domain_t h, const std::vector<double> &d, const std::vector<double> &rho)
+{
+    const lbdem_params &p = h->prm;
+    if (!p.body_force_auto) return;
+    bool all_per = p.periodic[0] && p.periodic[1] && p.periodic[2];
+    double s = 0.0;
+    if (all_per)
+        for (size_t i = 0; i < d.size(); ++i) s += (rho[i] - p.rho_f) * (M_PI * d[i] * d[i] * d[i] / 6.0);
+    s /= (double)h->geo.nc;
+    for (int a = 0; a < 3; ++a) h->phys.fb[a] = all_per ? -s * p.gravity[a] : 0.0;
+}
+
+template <typename R>
+void rebuild_particle_fields(lbdem_domain_t h)
+{
+    Desc D = h->desc();
+    Cells<R> C = h->cells<R>();
+    launch_zero_int(h->cnt, h->geo.nc, h->stream);
+    launch_bin_count(D, h->stream);
+    launch_bin_build(D, h->stream);
+    launch_gather_eps<R>(D, C, h->stream);
+    hip_check(hipGetLastError(), "particle field rebuild");
+}
+
+void rebuild(lbdem_domain_t h)
+{
+    if (h->prec == LBDEM_FP64) rebuild_particle_fields<double>(h);
+    else rebuild_particle_fields<float>(h);
+}
+
+// reallocate particle arrays for capacity `cap`, keeping nothing
+void alloc_particles(lbdem_domain_t h, int64_t cap)
+{
+    Parts &P = h->pt;
+    double **vec[] = {&P.x, &P.u, &P.w, &P.a, &P.Fam, &P.Fd, &P.Fpr, &P.Fc, &P.Fdem, &P.Tdem, &P.ustart, &P.xstart};
+    for (double **v : vec) {
+        h->dfree(*v);
+        *v = nullptr;
+    }
+    h->dfree(P.d);
+    h->dfree(P.rho);
+    h->dfree(h->list);
+    P.d = P.rho = nullptr;
+    h->list = nullptr;
+    P.cap = std::max<int64_t>(cap, 1);
+    for (double **v : vec) {
+        *v = (double *)h->dalloc(sizeof(double) * 3 * (size_t)P.cap);
+        hip_check(hipMemsetAsync(*v, 0, sizeof(double) * 3 * (size_t)P.cap, h->stream), "hipMemsetAsync");
+    }
+    P.d = (double *)h->dalloc(sizeof(double) * (size_t)P.cap);
+    P.rho = (double *)h->dalloc(sizeof(double) * (size_t)P.cap);
+    h->list = (int *)h->dalloc(sizeof(int) * (size_t)P.cap);
+    h->list_cap = P.cap;
+}
+
+// host AoS [n][3] <-> device SoA [3][cap]
+void upload_vec(lbdem_domain_t h, double *dev, const double *host, int64_t n)
+{
+    if (n == 0) return;
+    std::vector<double> buf(3 * (size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) buf[a * n + i] = host ? host[3 * i + a] : 0.0;
+    for (int a = 0; a < 3; ++a)
+        hip_check(hipMemcpyAsync(dev + a * h->pt.cap, buf.data() + a * n, sizeof(double) * n, hipMemcpyHostToDevice,
+                                 h->stream), "upload");
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+}
+
+void download_vec(lbdem_domain_t h, const double *dev, double *host, int64_t n)
+{
+    if (n == 0 || !host) return;
+    std::vector<double> buf(3 * (size_t)n);
+    for (int a = 0; a < 3; ++a)
+        hip_check(hipMemcpyAsync(buf.data() + a * n, dev + a * h->pt.cap, sizeof(double) * n, hipMemcpyDeviceToHost,
+                                 h->stream), "download");
+    hip_check(hipStreamSynchronize(h->stream), "sync");
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) host[3 * i + a] = buf[a * n + i];
+}
+
+struct HostParticles {
+    std::vector<double> x, u, w, a, d, rho;
+};
+
+HostParticles fetch_particles(lbdem_domain_t h)
+{
+    HostParticles hp;
+    const int64_t n = h->pt.np;
+    hp.x.resize(3 * n);
+    hp.u.resize(3 * n);
+    hp.w.resize(3 * n);
+    hp.a.resize(3 * n);
+    hp.d.resize(n);
+    hp.rho.resize(n);
+    download_vec(h, h->pt.x, hp.x.data(), n);
+    download_vec(h, h->pt.u, hp.u.data(), n);
+    download_vec(h, h->pt.w, hp.w.data(), n);
+    download_vec(h, h->pt.a, hp.a.data(), n);
+    if (n) {
+        hip_check(hipMemcpy(hp.d.data(), h->pt.d, sizeof(double) * n, hipMemcpyDeviceToHost), "download");
+        hip_check(hipMemcpy(hp.rho.data(), h->pt.rho, sizeof(double) * n, hipMemcpyDeviceToHost), "download");
+    }
+    return hp;
+}
+
+void put_particles(lbdem_domain_t h, const HostParticles &hp)
+{
+    const int64_t n = (int64_t)hp.d.size();
+    if (n > h->pt.cap) alloc_particles(h, std::max<int64_t>(n, 2 * h->pt.cap));
+    h->pt.np = n;
+    upload_vec(h, h->pt.x, hp.x.data(), n);
+    upload_vec(h, h->pt.u, hp.u.data(), n);
+    upload_vec(h, h->pt.w, hp.w.data(), n);
+    upload_vec(h, h->pt.a, hp.a.empty() ? nullptr : hp.a.data(), n);
+    if (n) {
+        hip_check(hipMemcpy(h->pt.d, hp.d.data(), sizeof(double) * n, hipMemcpyHostToDevice), "upload");
+        hip_check(hipMemcpy(h->pt.rho, hp.rho.data(), sizeof(double) * n, hipMemcpyHostToDevice), "upload");
+    }
+    h->dmax = 0.0;
+    for (double v : hp.d) h->dmax = std::max(h->dmax, v);
+    update_search(h);
+    update_body_force(h, hp.d, hp.rho);
+}
+
+void check_particles(lbdem_domain_t h, int64_t n, const double *x, const double *d, const double *rho)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(d[i] > 0.0) || !(rho[i] > 0.0) || !std::isfinite(d[i]) || !std::isfinite(rho[i]))
+            throw std::runtime_error("particle " + std::to_string(i) + ": diameter and density must be > 0");
+        for (int a = 0; a < 3; ++a) {
+            const double v = x[3 * i + a];
+            const double L = h->geo.n[a];
+            if (!std::isfinite(v)) throw std::runtime_error("particle " + std::to_string(i) + ": non-finite position");
+            if (h->geo.per[a] ? !(v >= 0.0 && v < L) : !(v > 0.0 && v < L))
+                throw std::runtime_error("particle " + std::to_string(i) + ": centre outside the domain");
+        }
+    }
+}
+
+template <typename R>
+void enqueue_step(lbdem_domain_t h)
+{
+    hipStream_t s = h->stream;
+    const Desc D = h->desc();
+    const Cells<R> C = h->cells<R>();
+    launch_cls(h, 1, [&] { launch_moments<R>(D, C, s); });
+    launch_cls(h, 2, [&] { launch_cellfields<R>(D, C, s); });
+    for (int k = 0; k < h->phys.n_int; ++k) {
+        launch_cls(h, 3, [&] { launch_part_am<R>(D, C, s); });
+        launch_cls(h, 4, [&] { launch_gather_am<R>(D, C, s); });
+        launch_cls(h, 3, [&] { launch_part_drag<R>(D, C, s); });
+        launch_cls(h, 4, [&] { launch_gather_fd<R>(D, C, s); });
+        for (int sub = 0; sub < h->phys.n_dem; ++sub) {
+            launch_cls(h, 5, [&] { launch_dem_force(D, s); });
+            launch_cls(h, 5, [&] { launch_integrate(D, sub == h->phys.n_dem - 1, s); });
+        }
+        launch_cls(h, 6, [&] { launch_bin_build(D, s); });
+        launch_cls(h, 4, [&] { launch_gather_eps<R>(D, C, s); });
+    }
+    launch_cls(h, 0, [&] { launch_stream_collide<R>(D, C, s); });
+    hip_check(hipGetLastError(), "kernel launch");
+    h->cur ^= 1;
+    h->step_host += 1;
+}
+
+template <typename R>
+void read_field_impl(lbdem_domain_t h, int field, double *dev_out)
+{
+    const int64_t nc = h->geo.nc;
+    const R *src = nullptr;
+    int ncomp = 1;
+    switch (field) {
+    case LBDEM_FIELD_DRHO: {
+        // moments of the current state
+        Desc D = h->desc();
+        Cells<R> C = h->cells<R>();
+        launch_moments<R>(D, C, h->stream);
+        src = (const R *)h->drho;
+        break;
+    }
+    case LBDEM_FIELD_J: src = (const R *)h->j; ncomp = 3; break;
+    case LBDEM_FIELD_EPS_F: src = (const R *)h->epsp; break;
+    case LBDEM_FIELD_F_ACC: src = (const R *)h->facc; ncomp = 3; break;
+    case LBDEM_FIELD_DUDT: src = (const R *)h->dudt; ncomp = 3; break;
+    case LBDEM_FIELD_GRADP: src = (const R *)h->gradp; ncomp = 3; break;
+    case LBDEM_FIELD_UPREV: src = (const R *)h->uprev; ncomp = 3; break;
+    case LBDEM_FIELD_PDF: src = (const R *)h->df[h->cur]; ncomp = 19; break;
+    default: throw std::runtime_error("unknown field id");
+    }
+    launch_to_double<R>(src, dev_out, ncomp * nc, h->stream);
+    hip_check(hipGetLastError(), "read_field");
+}
+
+int field_ncomp(int field)
+{
+    switch (field) {
+    case LBDEM_FIELD_DRHO:
+    case LBDEM_FIELD_EPS_F: return 1;
+    case LBDEM_FIELD_PDF: return 19;
+    default: return 3;
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *lbdem_last_error(lbdem_domain_t h) { return h ? h->err.c_str() : g_thread_err.c_str(); }
+
+lbdem_status lbdem_params_default(lbdem_params *p)
+{
+    if (!p) return fail(nullptr, LBDEM_E_INVALID, "null params");
+    std::memset(p, 0, sizeof(*p));
+    p->n[0] = p->n[1] = p->n[2] = 32;
+    p->periodic[0] = p->periodic[1] = p->periodic[2] = 1;
+    p->tau = 0.8;
+    p->rho_f = 1.0;
+    p->e_n = 0.88;
+    p->mu_c = 0.25;
+    p->T_c = 0.0;
+    p->h_c = 0.5;
+    p->h_min = 1e-5;
+    p->lub_stab = 1;
+    p->use_lub = 1;
+    p->use_am = 1;
+    p->n_int = 10;
+    p->n_dem = 1;
+    p->c_am = 0.5;
+    p->precision = LBDEM_FP64;
+    return LBDEM_OK;
+}
+
+lbdem_status lbdem_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *), void *ctx)
+{
+    if ((alloc == nullptr) != (free_fn == nullptr))
+        return fail(nullptr, LBDEM_E_INVALID, "allocator and free must both be set or both NULL");
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_alloc_ctx = ctx;
+    return LBDEM_OK;
+}
+
+lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_t *out)
+{
+    if (!p || !out) return fail(nullptr, LBDEM_E_INVALID, "null argument");
+    *out = nullptr;
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(nullptr, LBDEM_E_INVALID, "tau must be > 1/2");
+    for (int a = 0; a < 3; ++a)
+        if (p->n[a] < 1) return fail(nullptr, LBDEM_E_INVALID, "grid sizes must be >= 1");
+    if (p->n_int < 1 || p->n_dem < 1) return fail(nullptr, LBDEM_E_INVALID, "n_int and n_dem must be >= 1");
+    if (p->precision != LBDEM_FP64 && p->precision != LBDEM_FP32_DEV)
+        return fail(nullptr, LBDEM_E_INVALID, "unknown precision");
+    if (!(p->e_n > 0.0 && p->e_n <= 1.0)) return fail(nullptr, LBDEM_E_INVALID, "e_n must be in (0, 1]");
+    if (!(p->rho_f > 0.0)) return fail(nullptr, LBDEM_E_INVALID, "rho_f must be > 0");
+    const int64_t nc = (int64_t)p->n[0] * p->n[1] * p->n[2];
+    if (nc > ((int64_t)1 << 31) - 1) return fail(nullptr, LBDEM_E_INVALID, "too many cells (max 2^31-1)");
+    if ((nc + kScanPerBlock - 1) / kScanPerBlock > 1024 * 64)
+        return fail(nullptr, LBDEM_E_INVALID, "too many cells for the bin scan");
+
+    lbdem_domain_t h = new lbdem_domain();
+    h->prm = *p;
+    h->al = DevAlloc{g_alloc, g_free, g_alloc_ctx};
+    h->prec = p->precision;
+    for (int a = 0; a < 3; ++a) {
+        h->geo.n[a] = p->n[a];
+        h->geo.per[a] = p->periodic[a] ? 1 : 0;
+    }
+    h->geo.nc = nc;
+    resolve_phys(h);
+    lbdem_status st = guarded(nullptr, [&]() -> lbdem_status {
+        if (hip_stream) h->stream = (hipStream_t)hip_stream;
+        else {
+            hip_check(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking), "hipStreamCreate");
+            h->own_stream = true;
+        }
+        const size_t rs = h->rsize();
+        h->df[0] = h->dalloc(rs * 19 * nc);
+        h->df[1] = h->dalloc(rs * 19 * nc);
+        h->drho = h->dalloc(rs * nc);
+        h->j = h->dalloc(rs * 3 * nc);
+        h->uprev = h->dalloc(rs * 3 * nc);
+        h->dudt = h->dalloc(rs * 3 * nc);
+        h->gradp = h->dalloc(rs * 3 * nc);
+        h->epsp = h->dalloc(rs * nc);
+        h->fam = h->dalloc(rs * 3 * nc);
+        h->facc = h->dalloc(rs * 3 * nc);
+        h->cnt = (int *)h->dalloc(sizeof(int) * nc);
+        h->start = (int *)h->dalloc(sizeof(int) * (nc + 1));
+        h->bsum = (int *)h->dalloc(sizeof(int) * ((nc + kScanPerBlock - 1) / kScanPerBlock + 1));
+        h->flags = (int *)h->dalloc(sizeof(int) * 4);
+        h->stepc = (long long *)h->dalloc(sizeof(long long) * 2);
+        h->diag_part = (double *)h->dalloc(sizeof(double) * 12 * 1024);
+        h->diag_out = (double *)h->dalloc(sizeof(double) * 16);
+        for (void *q : {h->df[0], h->df[1]}) hip_check(hipMemsetAsync(q, 0, rs * 19 * nc, h->stream), "memset");
+        for (void *q : {h->drho, h->epsp}) hip_check(hipMemsetAsync(q, 0, rs * nc, h->stream), "memset");
+        for (void *q : {h->j, h->uprev, h->dudt, h->gradp, h->fam, h->facc})
+            hip_check(hipMemsetAsync(q, 0, rs * 3 * nc, h->stream), "memset");
+        hip_check(hipMemsetAsync(h->cnt, 0, sizeof(int) * nc, h->stream), "memset");
+        hip_check(hipMemsetAsync(h->start, 0, sizeof(int) * (nc + 1), h->stream), "memset");
+        hip_check(hipMemsetAsync(h->flags, 0, sizeof(int) * 4, h->stream), "memset");
+        hip_check(hipMemsetAsync(h->stepc, 0, sizeof(long long) * 2, h->stream), "memset");
+        alloc_particles(h, 64);
+        h->pt.np = 0;
+        update_search(h);
+        rebuild(h);
+        hip_check(hipStreamSynchronize(h->stream), "create sync");
+        return LBDEM_OK;
+    });
+    if (st != LBDEM_OK) {
+        lbdem_destroy(h);
+        return st;
+    }
+    *out = h;
+    return LBDEM_OK;
+}
+
+lbdem_status lbdem_destroy(lbdem_domain_t h)
+{
+    if (!h) return LBDEM_OK;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (auto &e : h->ev_pool) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    std::vector<void *> all = h->owned;
+    for (void *p : all) h->dfree(p);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+    return LBDEM_OK;
+}
+
+lbdem_status lbdem_add_particles(lbdem_domain_t h, int64_t n, const double *x, const double *u, const double *omega,
+                                 const double *d, const double *rho_p)
+{
+    if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
+    if (n < 0 || (n > 0 && (!x || !d || !rho_p))) return fail(h, LBDEM_E_INVALID, "bad particle arrays");
+    if (n == 0) return LBDEM_OK;
+    return guarded(h, [&]() -> lbdem_status {
+        check_particles(h, n, x, d, rho_p);
+        if (h->pt.np + n > ((int64_t)1 << 31) - 1) throw std::runtime_error("too many particles");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        HostParticles hp = fetch_particles(h);
+        const int64_t n0 = h->pt.np;
+        hp.x.insert(hp.x.end(), x, x + 3 * n);
+        if (u) hp.u.insert(hp.u.end(), u, u + 3 * n); else hp.u.resize(3 * (n0 + n), 0.0);
+        if (omega) hp.w.insert(hp.w.end(), omega, omega + 3 * n); else hp.w.resize(3 * (n0 + n), 0.0);
+        hp.a.resize(3 * (n0 + n), 0.0);
+        hp.d.insert(hp.d.end(), d, d + n);
+        hp.rho.insert(hp.rho.end(), rho_p, rho_p + n);
+        put_particles(h, hp);
+        rebuild(h);
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_step(lbdem_domain_t h, int64_t nsteps)
+{
+    if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
+    if (nsteps < 0) return fail(h, LBDEM_E_INVALID, "nsteps < 0");
+    return guarded(h, [&]() -> lbdem_status {
+        for (int64_t s = 0; s < nsteps; ++s) {
+            if (h->prec == LBDEM_FP64) enqueue_step<double>(h);
+            else enqueue_step<float>(h);
+        }
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_sync(lbdem_domain_t h)
+{
+    if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
+    return guarded(h, [&]() -> lbdem_status {
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        if (h->timing) harvest_timing(h);
+        int fl = 0;
+        hip_check(hipMemcpy(&fl, h->flags, sizeof(int), hipMemcpyDeviceToHost), "flags");
+        if (fl) {
+            std::string m = "unstable:";
+            if (fl & FLAG_WALL) m += " particle through a wall;";
+            if (fl & FLAG_SKIN) m += " particle moved beyond the search skin within a subcycle;";
+            if (fl & FLAG_NONFINITE) m += " non-finite particle state;";
+            if (fl & FLAG_EPS) m += " fluid fraction <= 0;";
+            return fail(h, LBDEM_E_UNSTABLE, m);
+        }
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_read_field(lbdem_domain_t h, int field, int mem_kind, double *out)
+{
+    if (!h || !out) return fail(h, LBDEM_E_INVALID, "null argument");
+    if (field < 0 || field > LBDEM_FIELD_PDF) return fail(h, LBDEM_E_INVALID, "unknown field");
+    return guarded(h, [&]() -> lbdem_status {
+        const int64_t n = field_ncomp(field) * h->geo.nc;
+        double *dst = mem_kind == LBDEM_MEM_DEVICE ? out : h->scratch(n);
+        if (h->prec == LBDEM_FP64) read_field_impl<double>(h, field, dst);
+        else read_field_impl<float>(h, field, dst);
+        if (mem_kind != LBDEM_MEM_DEVICE)
+            hip_check(hipMemcpyAsync(out, dst, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream), "copy");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_read_particles(lbdem_domain_t h, int mem_kind, double *x, double *u, double *omega, double *accel)
+{
+    if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
+    return guarded(h, [&]() -> lbdem_status {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        const int64_t n = h->pt.np;
+        const double *src[4] = {h->pt.x, h->pt.u, h->pt.w, h->pt.a};
+        double *dst[4] = {x, u, omega, accel};
+        for (int t = 0; t < 4; ++t) {
+            if (!dst[t]) continue;
+            if (mem_kind == LBDEM_MEM_DEVICE) {
+                std::vector<double> host(3 * n);
+                download_vec(h, src[t], host.data(), n);
+                hip_check(hipMemcpy(dst[t], host.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice), "copy");
+            } else {
+                download_vec(h, src[t], dst[t], n);
+            }
+        }
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_read_particle_forces(lbdem_domain_t h, double *F_am, double *F_d, double *F_pr, double *F_const)
+{
+    if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
+    return guarded(h, [&]() -> lbdem_status {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        const int64_t n = h->pt.np;
+        download_vec(h, h->pt.Fam, F_am, n);
+        download_vec(h, h->pt.Fd, F_d, n);
+        download_vec(h, h->pt.Fpr, F_pr, n);
+        download_vec(h, h->pt.Fc, F_const, n);
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_diagnostics(lbdem_domain_t h, lbdem_diag *out)
+{
+    if (!h || !out) return fail(h, LBDEM_E_INVALID, "null argument");
+    return guarded(h, [&]() -> lbdem_status {
+        Desc D = h->desc();
+        const int nb = diag_blocks(D);
+        if (h->prec == LBDEM_FP64) {
+            Cells<double> C = h->cells<double>();
+            launch_diag<double>(D, C, C.df_src, h->diag_part, nb, h->diag_out, h->stream);
+        } else {
+            Cells<float> C = h->cells<float>();
+            launch_diag<float>(D, C, C.df_src, h->diag_part, nb, h->diag_out, h->stream);
+        }
+        hip_check(hipGetLastError(), "diag");
+        double v[12];
+        hip_check(hipMemcpyAsync(v, h->diag_out, sizeof(v), hipMemcpyDeviceToHost, h->stream), "diag copy");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        const double nc = (double)h->geo.nc, np = (double)h->pt.np;
+        out->mass_dev = v[0];
+        for (int a = 0; a < 3; ++a) {
+            out->mom_fluid[a] = v[1 + a];
+            out->mom_part[a] = v[8 + a];
+        }
+        out->mean_eps_f = v[4] / nc;
+        out->min_eps_f = v[5];
+        out->u_ps = (np > 0 ? v[11] / np : 0.0) - v[6] / nc;
+        out->max_u = v[7];
+        out->step = h->step_host;
+        out->np = h->pt.np;
+        return LBDEM_OK;
+    });
+}
+
+int64_t lbdem_num_cells(lbdem_domain_t h) { return h ? h->geo.nc : 0; }
+int64_t lbdem_num_particles(lbdem_domain_t h) { return h ? h->pt.np : 0; }
+
+lbdem_status lbdem_get_state(lbdem_domain_t h, lbdem_state_view *v)
+{
+    if (!h || !v) return fail(h, LBDEM_E_INVALID, "null argument");
+    if (v->np < h->pt.np) {
+        const int64_t need = h->pt.np;
+        v->np = need;
+        return fail(h, LBDEM_E_INVALID, "particle arrays too small");
+    }
+    return guarded(h, [&]() -> lbdem_status {
+        const int64_t nc = h->geo.nc;
+        if (v->df) {
+            double *tmp = h->scratch(19 * nc);
+            if (h->prec == LBDEM_FP64) launch_to_double<double>((const double *)h->df[h->cur], tmp, 19 * nc, h->stream);
+            else launch_to_double<float>((const float *)h->df[h->cur], tmp, 19 * nc, h->stream);
+            hip_check(hipMemcpyAsync(v->df, tmp, sizeof(double) * 19 * nc, hipMemcpyDeviceToHost, h->stream), "copy");
+            hip_check(hipStreamSynchronize(h->stream), "sync");
+        }
+        if (v->uprev) {
+            double *tmp = h->scratch(3 * nc);
+            if (h->prec == LBDEM_FP64) launch_to_double<double>((const double *)h->uprev, tmp, 3 * nc, h->stream);
+            else launch_to_double<float>((const float *)h->uprev, tmp, 3 * nc, h->stream);
+            hip_check(hipMemcpyAsync(v->uprev, tmp, sizeof(double) * 3 * nc, hipMemcpyDeviceToHost, h->stream), "copy");
+            hip_check(hipStreamSynchronize(h->stream), "sync");
+        }
+        v->step = h->step_host;
+        v->np = h->pt.np;
+        const int64_t n = h->pt.np;
+        download_vec(h, h->pt.x, v->x, n);
+        download_vec(h, h->pt.u, v->u, n);
+        download_vec(h, h->pt.w, v->omega, n);
+        download_vec(h, h->pt.a, v->accel, n);
+        if (n && v->d) hip_check(hipMemcpy(v->d, h->pt.d, sizeof(double) * n, hipMemcpyDeviceToHost), "copy");
+        if (n && v->rho_p) hip_check(hipMemcpy(v->rho_p, h->pt.rho, sizeof(double) * n, hipMemcpyDeviceToHost), "copy");
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_set_state(lbdem_domain_t h, const lbdem_state_view *v)
+{
+    if (!h || !v || !v->df || !v->uprev) return fail(h, LBDEM_E_INVALID, "null argument");
+    if (v->np < 0 || (v->np > 0 && (!v->x || !v->u || !v->omega || !v->d || !v->rho_p)))
+        return fail(h, LBDEM_E_INVALID, "bad particle arrays");
+    return guarded(h, [&]() -> lbdem_status {
+        const int64_t nc = h->geo.nc, n = v->np;
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) {
+                const double x = v->x[3 * i + a];
+                if (!std::isfinite(x) || (h->geo.per[a] ? !(x >= 0.0 && x < h->geo.n[a]) : !(x > 0.0 && x < h->geo.n[a])))
+                    throw std::runtime_error("particle " + std::to_string(i) + ": centre outside the domain");
+            }
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        double *tmp = h->scratch(19 * nc);
+        hip_check(hipMemcpy(tmp, v->df, sizeof(double) * 19 * nc, hipMemcpyHostToDevice), "copy");
+        if (h->prec == LBDEM_FP64) launch_from_double<double>(tmp, (double *)h->df[h->cur], 19 * nc, h->stream);
+        else launch_from_double<float>(tmp, (float *)h->df[h->cur], 19 * nc, h->stream);
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        hip_check(hipMemcpy(tmp, v->uprev, sizeof(double) * 3 * nc, hipMemcpyHostToDevice), "copy");
+        if (h->prec == LBDEM_FP64) launch_from_double<double>(tmp, (double *)h->uprev, 3 * nc, h->stream);
+        else launch_from_double<float>(tmp, (float *)h->uprev, 3 * nc, h->stream);
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        HostParticles hp;
+        hp.x.assign(v->x, v->x + 3 * n);
+        hp.u.assign(v->u, v->u + 3 * n);
+        hp.w.assign(v->omega, v->omega + 3 * n);
+        if (v->accel) hp.a.assign(v->accel, v->accel + 3 * n); else hp.a.assign(3 * n, 0.0);
+        hp.d.assign(v->d, v->d + n);
+        hp.rho.assign(v->rho_p, v->rho_p + n);
+        put_particles(h, hp);
+        h->step_host = v->step;
+        launch_set_step(h->stepc, (long long)v->step, h->stream);
+        hip_check(hipMemsetAsync(h->flags, 0, sizeof(int) * 4, h->stream), "memset");
+        rebuild(h);
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        return LBDEM_OK;
+    });
+}
+
+namespace {
+struct BlobHeader {
+    char magic[8];
+    int32_t version, precision;
+    int32_t n[3], periodic[3];
+    int64_t step, np;
+};
+}  // namespace
+
+lbdem_status lbdem_save_state(lbdem_domain_t h, void *blob, size_t *size)
+{
+    if (!h || !size) return fail(h, LBDEM_E_INVALID, "null argument");
+    const int64_t nc = h->geo.nc, n = h->pt.np;
+    const size_t need = sizeof(BlobHeader) + sizeof(double) * (size_t)(22 * nc + 14 * n);
+    if (!blob) {
+        *size = need;
+        return LBDEM_OK;
+    }
+    if (*size < need) return fail(h, LBDEM_E_INVALID, "blob too small");
+    BlobHeader hd{};
+    std::memcpy(hd.magic, "LBDEMST1", 8);
+    hd.version = 1;
+    hd.precision = h->prec;
+    for (int a = 0; a < 3; ++a) {
+        hd.n[a] = h->geo.n[a];
+        hd.periodic[a] = h->geo.per[a];
+    }
+    hd.step = h->step_host;
+    hd.np = n;
+    std::memcpy(blob, &hd, sizeof(hd));
+    double *p = (double *)((char *)blob + sizeof(hd));
+    lbdem_state_view v{};
+    v.df = p;
+    v.uprev = p + 19 * nc;
+    double *q = p + 22 * nc;
+    v.x = q; v.u = q + 3 * n; v.omega = q + 6 * n; v.accel = q + 9 * n; v.d = q + 12 * n; v.rho_p = q + 13 * n;
+    v.np = n;
+    *size = need;
+    return lbdem_get_state(h, &v);
+}
+
+lbdem_status lbdem_load_state(lbdem_domain_t h, const void *blob, size_t size)
+{
+    if (!h || !blob) return fail(h, LBDEM_E_INVALID, "null argument");
+    if (size < sizeof(BlobHeader)) return fail(h, LBDEM_E_INVALID, "blob too small");
+    BlobHeader hd;
+    std::memcpy(&hd, blob, sizeof(hd));
+    if (std::memcmp(hd.magic, "LBDEMST1", 8) != 0 || hd.version != 1) return fail(h, LBDEM_E_INVALID, "not a state blob");
+    for (int a = 0; a < 3; ++a)
+        if (hd.n[a] != h->geo.n[a] || hd.periodic[a] != h->geo.per[a])
+            return fail(h, LBDEM_E_INVALID, "blob shape does not match the domain");
+    const int64_t nc = h->geo.nc, n = hd.np;
+    if (n < 0 || size < sizeof(BlobHeader) + sizeof(double) * (size_t)(22 * nc + 14 * n))
+        return fail(h, LBDEM_E_INVALID, "blob truncated");
+    const double *p = (const double *)((const char *)blob + sizeof(hd));
+    lbdem_state_view v{};
+    v.df = (double *)p;
+    v.uprev = (double *)(p + 19 * nc);
+    const double *q = p + 22 * nc;
+    v.x = (double *)q; v.u = (double *)(q + 3 * n); v.omega = (double *)(q + 6 * n);
+    v.accel = (double *)(q + 9 * n); v.d = (double *)(q + 12 * n); v.rho_p = (double *)(q + 13 * n);
+    v.np = n;
+    v.step = hd.step;
+    return lbdem_set_state(h, &v);
+}
+
+lbdem_status lbdem_set_timing(lbdem_domain_t h, int on)
+{
+    if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
+    return guarded(h, [&]() -> lbdem_status {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        if (h->timing) harvest_timing(h);
+        h->timing = on != 0;
+        for (int c = 0; c < 8; ++c) {
+            h->cls_ms[c] = 0.0;
+            h->cls_n[c] = 0;
+        }
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_kernel_time(lbdem_domain_t h, int cls, double *ms_total, int64_t *launches)
+{
+    if (!h || cls < 0 || cls >= 8) return fail(h, LBDEM_E_INVALID, "bad argument");
+    return guarded(h, [&]() -> lbdem_status {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        if (h->timing) harvest_timing(h);
+        if (ms_total) *ms_total = h->cls_ms[cls];
+        if (launches) *launches = h->cls_n[cls];
+        return LBDEM_OK;
+    });
+}
+
+}  // extern "C"

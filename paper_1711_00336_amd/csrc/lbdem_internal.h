@@ -1,0 +1,107 @@
+// Internal declarations shared by the HIP kernels and the host runtime of
+// the coupled LBM-DEM library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lbdem {
+
+// Lattice geometry: cell (i,j,k) centred at (i+1/2, j+1/2, k+1/2),
+// flat index i + nx*(j + ny*k). Non-periodic axes have walls at 0 and n.
+struct Geo {
+    int n[3];
+    int per[3];
+    int64_t nc;
+};
+
+// Model parameters in lattice units, resolved on the host.
+struct Phys {
+    double tau, omega;          // BGK relaxation time and its inverse
+    double rho_f, mu;           // closure density, dynamic viscosity (tau-1/2)/3 rho_f
+    double g[3], fb[3];         // particle gravity, fluid body-force density
+    double e_n, mu_c, T_c, h_c, h_min;
+    int lub_stab, use_lub, use_am;
+    int n_int, n_dem;
+    double dt_int, dt_dem, c_am;
+    double skin;                // allowed displacement within one subcycle
+    int rbin;                   // DEM search radius in cells
+};
+
+// Cell fields, [ncomp][nc] each. R = float (FP32 deviations) or double.
+template <typename R>
+struct Cells {
+    R *df_src, *df_dst;         // [19][nc] f_q - w_q
+    R *drho;                    // rho - 1 at step start
+    R *j;                       // [3] sum_q c_q f_q at step start
+    R *uprev;                   // [3] u_f of the previous step
+    R *dudt;                    // [3] Du_f/Dt
+    R *gradp;                   // [3] grad P
+    R *epsp;                    // solid fraction 1 - eps_f of the current positions
+    R *fam;                     // [3] -sum_p D F_am of the current subcycle
+    R *facc;                    // [3] subcycle mean of f_ext
+};
+
+// 1-cell bins: particles sorted by the cell of their position.
+struct Bins {
+    int *cnt;                   // [nc] counts (zero between builds)
+    int *start;                 // [nc+1] exclusive prefix of cnt
+    int *list;                  // [np] particle indices, ascending within a cell
+    int *bsum;                  // scan block sums
+};
+
+// Particles, SoA: vectors [3][cap] (component a of particle i at a*cap+i).
+struct Parts {
+    int64_t np, cap;
+    double *x, *u, *w, *a;      // position, velocity, angular velocity, du/dt of last subcycle
+    double *d, *rho;            // diameter, density
+    double *Fam, *Fd, *Fpr, *Fc;// last subcycle's fluid forces and F_const
+    double *Fdem, *Tdem;        // contact + lubrication force and torque of the substep
+    double *ustart, *xstart;    // velocity / position at subcycle start
+};
+
+struct Desc {
+    Geo g;
+    Phys p;
+    Bins b;
+    Parts pt;
+    int *flags;                 // error bits
+    long long *stepc;           // device step counter
+};
+
+enum : int {
+    FLAG_WALL = 1,              // particle centre through a wall
+    FLAG_SKIN = 2,              // moved more than the skin within a subcycle
+    FLAG_NONFINITE = 4,
+    FLAG_EPS = 8                // eps_f <= 0
+};
+
+constexpr int kBlock = 256;
+constexpr int kScanItems = 8;   // per thread in the block scan
+constexpr int kScanPerBlock = kBlock * kScanItems;
+
+// -- launchers (lbdem_kernels.hip) -----------------------------------------
+template <typename R> void launch_moments(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_cellfields(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_part_am(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_gather_am(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_gather_fd(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s);
+template <typename R> void launch_to_double(const R *src, double *dst, int64_t n, hipStream_t s);
+template <typename R> void launch_from_double(const double *src, R *dst, int64_t n, hipStream_t s);
+template <typename R>
+void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials, int nblk, double *out,
+                 hipStream_t s);
+int diag_blocks(const Desc &D);
+
+void launch_dem_force(const Desc &D, hipStream_t s);
+void launch_integrate(const Desc &D, int last_substep, hipStream_t s);
+void launch_bin_count(const Desc &D, hipStream_t s);
+void launch_bin_build(const Desc &D, hipStream_t s);   // scan + place + per-cell sort
+void launch_zero_int(int *p, int64_t n, hipStream_t s);
+void launch_set_step(long long *stepc, long long v, hipStream_t s);
+
+}  // namespace lbdem

@@ -1,0 +1,1062 @@
+// HIP kernels (gfx950) of one coupled LBM-DEM time step, following Alg. 1
+// of Rettinger & Ruede (arXiv 1711.00336, Sec. 3.3).
+//
+// Layout: cell fields are structure-of-arrays [ncomp][nc] with x fastest, so
+// a 64-lane wavefront touches 64 consecutive cells of one component. PDFs
+// are stored as deviations f_q - w_q (rho_0 = 1) in float or double.
+// Particles are SoA [3][cap] doubles. Particle -> cell transfers are gathers:
+// every cell sums the particles of its 3x3x3 neighbouring 1-cell bins, so
+// the result is deterministic and needs no floating-point atomics.
+#include "lbdem_internal.h"
+
+#include <cmath>
+
+namespace lbdem {
+
+// ---------------------------------------------------------------------------
+// D3Q19 velocity set: 0 rest; 1..6 +x,-x,+y,-y,+z,-z; 7..18 face diagonals
+// (1,1,0),(-1,-1,0),(1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),
+// (0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1). Weights 1/3, 1/18, 1/36.
+// Written as constexpr selectors so that unrolled loops fold to immediates.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int CX(int q)
+{
+    return (q == 1 || q == 7 || q == 9 || q == 11 || q == 13) ? 1
+         : (q == 2 || q == 8 || q == 10 || q == 12 || q == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int CY(int q)
+{
+    return (q == 3 || q == 7 || q == 10 || q == 15 || q == 17) ? 1
+         : (q == 4 || q == 8 || q == 9 || q == 16 || q == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int CZ(int q)
+{
+    return (q == 5 || q == 11 || q == 14 || q == 15 || q == 18) ? 1
+         : (q == 6 || q == 12 || q == 13 || q == 16 || q == 17) ? -1 : 0;
+}
+__host__ __device__ constexpr int CC(int q, int a) { return a == 0 ? CX(q) : a == 1 ? CY(q) : CZ(q); }
+__host__ __device__ constexpr double WQ(int q) { return q == 0 ? 1.0 / 3.0 : q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0; }
+__host__ __device__ constexpr int OPP(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+__device__ __forceinline__ int64_t gidx(int64_t per_block = kBlock)
+{
+    return (int64_t)blockIdx.x * per_block + threadIdx.x;
+}
+
+__device__ __forceinline__ void cell_coords(const Geo &g, int64_t c, int &i, int &j, int &k)
+{
+    i = (int)(c % g.n[0]);
+    int64_t r = c / g.n[0];
+    j = (int)(r % g.n[1]);
+    k = (int)(r / g.n[1]);
+}
+
+__device__ __forceinline__ int64_t cidx(const Geo &g, int i, int j, int k)
+{
+    return (int64_t)i + (int64_t)g.n[0] * ((int64_t)j + (int64_t)g.n[1] * k);
+}
+
+// ---------------------------------------------------------------------------
+// Roma et al. three-point kernel (Sec. 3.1.2, Eq. filter_def), applied per
+// axis; the 3-D weight is the product over axes. Walled axes drop cells
+// outside the domain and renormalise the rest to unit sum.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double roma(double r)
+{
+    r = fabs(r);
+    if (r < 0.5) return (1.0 + sqrt(1.0 - 3.0 * r * r)) / 3.0;
+    if (r < 1.5) return (5.0 - 3.0 * r - sqrt(1.0 - 3.0 * (1.0 - r) * (1.0 - r))) / 6.0;
+    return 0.0;
+}
+
+struct AxisSt {
+    int idx[3];
+    double w[3];
+    int m;
+};
+
+__device__ __forceinline__ void axis_stencil(double xp, int n, int per, AxisSt &s)
+{
+    const int b = (int)floor(xp);
+    double sum = 0.0;
+    s.m = 0;
+#pragma unroll
+    for (int o = -1; o <= 1; ++o) {
+        const int i = b + o;
+        const double w = roma((double)i + 0.5 - xp);
+        if (per) {
+            s.idx[s.m] = wrapi(i, n);
+            s.w[s.m] = w;
+            s.m++;
+        } else if (i >= 0 && i < n) {
+            s.idx[s.m] = i;
+            s.w[s.m] = w;
+            sum += w;
+            s.m++;
+        }
+    }
+    if (!per)
+        for (int t = 0; t < s.m; ++t) s.w[t] /= sum;
+}
+
+// weight of cell coordinate ic in the stencil of a particle at xp (one axis)
+__device__ __forceinline__ double axis_weight(double xp, int ic, int n, int per)
+{
+    const int b = (int)floor(xp);
+    if (per) {
+        double w = 0.0;
+#pragma unroll
+        for (int o = -1; o <= 1; ++o)
+            if (wrapi(b + o, n) == ic) w += roma((double)(b + o) + 0.5 - xp);
+        return w;
+    }
+    if (ic < b - 1 || ic > b + 1) return 0.0;
+    double sum = 0.0;
+#pragma unroll
+    for (int o = -1; o <= 1; ++o) {
+        const int i = b + o;
+        if (i >= 0 && i < n) sum += roma((double)i + 0.5 - xp);
+    }
+    return roma((double)ic + 0.5 - xp) / sum;
+}
+
+// distinct wrapped coordinates c-r..c+r on one axis (walled: in range only)
+__device__ __forceinline__ int axis_range(int c, int r, int n, int per, int *out, int cap)
+{
+    int m = 0;
+    if (per) {
+        if (2 * r + 1 >= n) {
+            for (int i = 0; i < n && m < cap; ++i) out[m++] = i;
+        } else {
+            for (int o = -r; o <= r; ++o) out[m++] = wrapi(c + o, n);
+        }
+    } else {
+        for (int o = -r; o <= r; ++o) {
+            const int i = c + o;
+            if (i >= 0 && i < n) out[m++] = i;
+        }
+    }
+    return m;
+}
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+__device__ __forceinline__ int64_t particle_cell(const Geo &g, double x, double y, double z)
+{
+    const int i = clampi((int)floor(x), 0, g.n[0] - 1);
+    const int j = clampi((int)floor(y), 0, g.n[1] - 1);
+    const int k = clampi((int)floor(z), 0, g.n[2] - 1);
+    return cidx(g, i, j, k);
+}
+
+__device__ __forceinline__ double sphere_volume(double d) { return M_PI * d * d * d / 6.0; }
+
+// ---------------------------------------------------------------------------
+// a1: moments of the post-stream PDFs (Eq. MacVel): rho - 1 = sum df,
+// j = sum c df (exact with deviations since sum_q w_q c_q = 0).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_moments(Desc D, Cells<R> C)
+{
+    const int64_t nc = D.g.nc;
+    const int64_t c = gidx();
+    if (c >= nc) return;
+    R r = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        const R f = C.df_src[q * nc + c];
+        r += f;
+        if (CX(q) > 0) jx += f; else if (CX(q) < 0) jx -= f;
+        if (CY(q) > 0) jy += f; else if (CY(q) < 0) jy -= f;
+        if (CZ(q) > 0) jz += f; else if (CZ(q) < 0) jz -= f;
+    }
+    C.drho[c] = r;
+    C.j[c] = jx;
+    C.j[nc + c] = jy;
+    C.j[2 * nc + c] = jz;
+}
+
+// neighbour x + c_q with the wall ghost rule: the mirrored in-domain cell;
+// a velocity flips sign once per mirrored axis (no-slip at the half-way
+// plane), a scalar keeps its value.
+__device__ __forceinline__ int64_t ghost(const Geo &g, int i, int j, int k, int q, double &sign)
+{
+    int t[3] = {i + CX(q), j + CY(q), k + CZ(q)};
+    sign = 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (t[a] < 0 || t[a] >= g.n[a]) {
+            if (g.per[a]) t[a] = wrapi(t[a], g.n[a]);
+            else {
+                t[a] = t[a] < 0 ? 0 : g.n[a] - 1;
+                sign = -sign;
+            }
+        }
+    }
+    return cidx(g, t[0], t[1], t[2]);
+}
+
+// ---------------------------------------------------------------------------
+// a2/a3: per-step cell fields (Alg. 1, "Evaluate and store Du_f/Dt"):
+//   u_f^n = (j + eps_f f_b / 2) / (rho eps_f)      (Eq. MacVel, u_f = u_bar/eps_f)
+//   Du_f/Dt = (u_f^n - u_prev) + (u_f^n . grad_L) u_f^n (0 time part at step 0)
+//   grad P = (1/c_s^2) sum_q w_q c_q P(x+c_q) = sum_q w_q c_q (rho-1)(x+c_q)
+// with the lattice gradient of Sec. 3.2.3. Also resets f_acc.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_cellfields(Desc D, Cells<R> C)
+{
+    const int64_t nc = D.g.nc;
+    const int64_t c = gidx();
+    if (c >= nc) return;
+    int i, j, k;
+    cell_coords(D.g, c, i, j, k);
+    const double fb0 = D.p.fb[0], fb1 = D.p.fb[1], fb2 = D.p.fb[2];
+    double G[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    double gp[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        double sg;
+        const int64_t nb = ghost(D.g, i, j, k, q, sg);
+        const double e = 1.0 - (double)C.epsp[nb];
+        const double rho = 1.0 + (double)C.drho[nb];
+        const double u0 = ((double)C.j[nb] + 0.5 * e * fb0) / (rho * e);
+        const double u1 = ((double)C.j[nc + nb] + 0.5 * e * fb1) / (rho * e);
+        const double u2 = ((double)C.j[2 * nc + nb] + 0.5 * e * fb2) / (rho * e);
+        const double dr = (double)C.drho[nb];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (CC(q, a) == 0) continue;
+            const double wc = CC(q, a) > 0 ? WQ(q) : -WQ(q);
+            G[a][0] += wc * (sg * u0);
+            G[a][1] += wc * (sg * u1);
+            G[a][2] += wc * (sg * u2);
+            gp[a] += wc * dr;
+        }
+    }
+    const double e = 1.0 - (double)C.epsp[c];
+    const double rho = 1.0 + (double)C.drho[c];
+    double un[3];
+    un[0] = ((double)C.j[c] + 0.5 * e * fb0) / (rho * e);
+    un[1] = ((double)C.j[nc + c] + 0.5 * e * fb1) / (rho * e);
+    un[2] = ((double)C.j[2 * nc + c] + 0.5 * e * fb2) / (rho * e);
+    const bool have_prev = *D.stepc > 0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        double conv = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) conv += un[a] * (3.0 * G[a][b]);
+        const double dtu = have_prev ? (un[b] - (double)C.uprev[b * nc + c]) : 0.0;
+        C.dudt[b * nc + c] = (R)(dtu + conv);
+        C.gradp[b * nc + c] = (R)gp[b];
+        C.uprev[b * nc + c] = (R)un[b];
+        C.facc[b * nc + c] = (R)0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a4: added mass (Table 1): F_am = C_am rho_f V (Du_f/Dt|_p - du_p/dt), the
+// fluid derivative interpolated with Eq. interpolation. Also records the
+// subcycle-start velocity and position.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
+{
+    const int64_t i = gidx();
+    const Parts &P = D.pt;
+    if (i >= P.np) return;
+    const int64_t cap = P.cap, nc = D.g.nc;
+    const double xp[3] = {P.x[i], P.x[cap + i], P.x[2 * cap + i]};
+    AxisSt s[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) axis_stencil(xp[a], D.g.n[a], D.g.per[a], s[a]);
+    double Du[3] = {0.0, 0.0, 0.0};
+    for (int cz = 0; cz < s[2].m; ++cz)
+        for (int cy = 0; cy < s[1].m; ++cy)
+            for (int cx = 0; cx < s[0].m; ++cx) {
+                const int64_t cell = cidx(D.g, s[0].idx[cx], s[1].idx[cy], s[2].idx[cz]);
+                const double w = s[0].w[cx] * s[1].w[cy] * s[2].w[cz];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Du[b] += w * (double)C.dudt[b * nc + cell];
+            }
+    const double V = sphere_volume(P.d[i]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const double F = D.p.use_am ? D.p.c_am * D.p.rho_f * V * (Du[b] - P.a[b * cap + i]) : 0.0;
+        P.Fam[b * cap + i] = F;
+        P.ustart[b * cap + i] = P.u[b * cap + i];
+        P.xstart[b * cap + i] = xp[b];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gather of a particle quantity to one cell (Eq. distribution_filter with
+// D = I): s = sum_p D(x, x_p) v_p over particles in the 27 neighbouring bins.
+// ---------------------------------------------------------------------------
+template <int NV, typename F>
+__device__ __forceinline__ void gather_cell(const Desc &D, int i, int j, int k, const F &val, double *s)
+{
+    int cx[3], cy[3], cz[3];
+    const int mx = axis_range(i, 1, D.g.n[0], D.g.per[0], cx, 3);
+    const int my = axis_range(j, 1, D.g.n[1], D.g.per[1], cy, 3);
+    const int mz = axis_range(k, 1, D.g.n[2], D.g.per[2], cz, 3);
+    const int64_t cap = D.pt.cap;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) s[t] = 0.0;
+    for (int a = 0; a < mz; ++a)
+        for (int b = 0; b < my; ++b)
+            for (int c = 0; c < mx; ++c) {
+                const int64_t bin = cidx(D.g, cx[c], cy[b], cz[a]);
+                const int p0 = D.b.start[bin], p1 = D.b.start[bin + 1];
+                for (int t = p0; t < p1; ++t) {
+                    const int p = D.b.list[t];
+                    const double wx = axis_weight(D.pt.x[p], i, D.g.n[0], D.g.per[0]);
+                    const double wy = axis_weight(D.pt.x[cap + p], j, D.g.n[1], D.g.per[1]);
+                    const double wz = axis_weight(D.pt.x[2 * cap + p], k, D.g.n[2], D.g.per[2]);
+                    const double w = wx * wy * wz;
+                    if (w == 0.0) continue;
+                    double v[NV];
+                    val(p, v);
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) s[q] += w * v[q];
+                }
+            }
+}
+
+// fam = -sum_p D F_am (the added-mass part of f_p->f, Eq. forces_pf)
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_gather_am(Desc D, Cells<R> C)
+{
+    const int64_t nc = D.g.nc;
+    const int64_t c = gidx();
+    if (c >= nc) return;
+    int i, j, k;
+    cell_coords(D.g, c, i, j, k);
+    const int64_t cap = D.pt.cap;
+    const double *Fam = D.pt.Fam;
+    double s[3];
+    gather_cell<3>(D, i, j, k, [&](int p, double *v) {
+        v[0] = Fam[p];
+        v[1] = Fam[cap + p];
+        v[2] = Fam[2 * cap + p];
+    }, s);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) C.fam[b * nc + c] = (R)(-s[b]);
+}
+
+// ---------------------------------------------------------------------------
+// a6: pressure-gradient force, drag, gravity + buoyancy (Table 1, Sec. 3.1.2)
+// with u_f re-evaluated from f_ext = eps_f f_b + f_am (Sec. 3.2.3 stability
+// measures; Alg. 1 "Reevaluate u_f").
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double drag_factor(double Re, double ep)
+{
+    const double e1 = 1.0 - ep;
+    const double cd0 = 1.0 + 0.15 * (Re > 0.0 ? pow(Re, 0.687) : 0.0);
+    const double A = 5.81 * ep / (e1 * e1 * e1) + 0.48 * (ep > 0.0 ? cbrt(ep) : 0.0) / (e1 * e1 * e1 * e1);
+    const double B = ep * ep * ep * Re * (0.95 + 0.61 * ep * ep * ep / (e1 * e1));
+    const double cd = e1 * (cd0 / (e1 * e1 * e1) + A + B);
+    return e1 * cd;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_part_drag(Desc D, Cells<R> C)
+{
+    const int64_t i = gidx();
+    const Parts &P = D.pt;
+    if (i >= P.np) return;
+    const int64_t cap = P.cap, nc = D.g.nc;
+    const double xp[3] = {P.x[i], P.x[cap + i], P.x[2 * cap + i]};
+    AxisSt s[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) axis_stencil(xp[a], D.g.n[a], D.g.per[a], s[a]);
+    double uf[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, ep = 0.0;
+    for (int cz = 0; cz < s[2].m; ++cz)
+        for (int cy = 0; cy < s[1].m; ++cy)
+            for (int cx = 0; cx < s[0].m; ++cx) {
+                const int64_t cell = cidx(D.g, s[0].idx[cx], s[1].idx[cy], s[2].idx[cz]);
+                const double w = s[0].w[cx] * s[1].w[cy] * s[2].w[cz];
+                const double epc = (double)C.epsp[cell];
+                const double e = 1.0 - epc;
+                const double rho = 1.0 + (double)C.drho[cell];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    const double fext = e * D.p.fb[b] + (double)C.fam[b * nc + cell];
+                    const double ub = ((double)C.j[b * nc + cell] + 0.5 * fext) / (rho * e);
+                    uf[b] += w * ub;
+                    gp[b] += w * (double)C.gradp[b * nc + cell];
+                }
+                ep += w * epc;
+            }
+    const double d = P.d[i];
+    const double V = sphere_volume(d);
+    double wv[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) wv[b] = uf[b] - P.u[b * cap + i];
+    const double wn = sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+    const double Re = (1.0 - ep) * D.p.rho_f * d * wn / D.p.mu;
+    const double fac = 3.0 * M_PI * d * D.p.mu * drag_factor(Re, ep);
+    const double rp = P.rho[i];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const double Fpr = -V * gp[b];
+        const double Fd = fac * wv[b];
+        const double fgb = (rp - D.p.rho_f) * V * D.p.g[b];
+        P.Fpr[b * cap + i] = Fpr;
+        P.Fd[b * cap + i] = Fd;
+        P.Fc[b * cap + i] = Fd + Fpr + P.Fam[b * cap + i] + fgb;
+    }
+}
+
+// f_acc += (eps_f f_b + f_am - sum_p D F_d) / n_int   (Alg. 1, mean f_ext)
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_gather_fd(Desc D, Cells<R> C)
+{
+    const int64_t nc = D.g.nc;
+    const int64_t c = gidx();
+    if (c >= nc) return;
+    int i, j, k;
+    cell_coords(D.g, c, i, j, k);
+    const int64_t cap = D.pt.cap;
+    const double *Fd = D.pt.Fd;
+    double s[3];
+    gather_cell<3>(D, i, j, k, [&](int p, double *v) {
+        v[0] = Fd[p];
+        v[1] = Fd[cap + p];
+        v[2] = Fd[2 * cap + p];
+    }, s);
+    const double e = 1.0 - (double)C.epsp[c];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const double fext = e * D.p.fb[b] + (double)C.fam[b * nc + c] - s[b];
+        C.facc[b * nc + c] = (R)((double)C.facc[b * nc + c] + fext * D.p.dt_int);
+    }
+}
+
+// a9: solid fraction of the current positions (Eq. fluid_volume_fraction)
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_gather_eps(Desc D, Cells<R> C)
+{
+    const int64_t nc = D.g.nc;
+    const int64_t c = gidx();
+    if (c >= nc) return;
+    int i, j, k;
+    cell_coords(D.g, c, i, j, k);
+    const double *d = D.pt.d;
+    double s[1];
+    gather_cell<1>(D, i, j, k, [&](int p, double *v) { v[0] = sphere_volume(d[p]); }, s);
+    const double e = 1.0 - s[0];
+    if (!(e > 0.0) || !isfinite(e)) atomicOr(D.flags, FLAG_EPS);
+    C.epsp[c] = (R)s[0];
+}
+
+// ---------------------------------------------------------------------------
+// a8: DEM (Sec. 3.1.1) + lubrication (Sec. 3.1.3) forces of one substep.
+// ---------------------------------------------------------------------------
+struct PV {
+    double r, m, d;
+    double x[3], u[3], w[3];
+};
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// spring-dashpot normal force and Coulomb-limited tangential force; torque
+// about the centre is (d_i/2) n x F^t (the moment of F^t at the contact point)
+__device__ __forceinline__ void contact(const Phys &p, double delta, const double n[3], const double ur[3],
+                                        double mij, double ri, double F[3], double T[3])
+{
+    const double L = log(p.e_n);
+    const double kn = mij * (M_PI * M_PI + L * L) / (p.T_c * p.T_c);
+    const double xi = -2.0 * L * mij / p.T_c;
+    const double urn_s = dot3(ur, n);
+    double urn[3], urt[3], Fn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        urn[a] = urn_s * n[a];
+        urt[a] = ur[a] - urn[a];
+        Fn[a] = -kn * delta * n[a] - xi * urn[a];
+    }
+    const double urt_n = sqrt(dot3(urt, urt));
+    double Ft[3] = {0.0, 0.0, 0.0};
+    if (urt_n > 0.0) {
+        const double fn_n = sqrt(dot3(Fn, Fn));
+        const double mag = fmin(p.mu_c * fn_n, xi * urt_n);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Ft[a] = -mag * urt[a] / urt_n;
+    }
+    double tq[3];
+    cross3(n, Ft, tq);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        F[a] += Fn[a] + Ft[a];
+        T[a] += ri * tq[a];
+    }
+}
+
+// Eq. lubrication_force, applied for h < h_c with h := max(h, h_min) and,
+// when lub_stab is set, h >= 3 pi mu <d>^2 dt_DEM / (8 m_ij)
+__device__ __forceinline__ void lubrication(const Phys &p, double h, double dm, double mij, const double n[3],
+                                            const double upr[3], double F[3])
+{
+    if (!(h < p.h_c)) return;
+    const double mu = p.mu;
+    double he = fmax(h, p.h_min);
+    if (p.lub_stab) he = fmax(he, 3.0 * M_PI * mu * dm * dm * p.dt_dem / (8.0 * mij));
+    const double Lg = log(dm / (2.0 * he));
+    const double asq = 1.5 * M_PI * mu * dm * (dm / (4.0 * he) + (18.0 / 40.0) * Lg + (9.0 / 84.0) * (he / dm) * Lg);
+    const double ash = 0.5 * M_PI * mu * dm * Lg * (dm + he) * (dm + he) / 4.0;
+    const double un = dot3(upr, n);
+    const double s = 2.0 / (he + dm);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a] += -asq * un * n[a] - ash * s * s * (upr[a] - un * n[a]);
+}
+
+__device__ __forceinline__ void pair_interaction(const Phys &p, const PV &pi, const PV &pj, const double dx[3],
+                                                 double F[3], double T[3])
+{
+    const double dist2 = dot3(dx, dx);
+    const double reach = pi.r + pj.r + (p.use_lub ? fmax(p.h_c, 0.0) : 0.0);
+    if (dist2 >= reach * reach) return;
+    const double dist = sqrt(dist2);
+    const double n[3] = {dx[0] / dist, dx[1] / dist, dx[2] / dist};
+    const double delta = pi.r + pj.r - dist;
+    const double mij = pi.m * pj.m / (pi.m + pj.m);
+    if (delta > 0.0) {
+        double s[3], ur[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) s[a] = pi.r * pi.w[a] + pj.r * pj.w[a];
+        cross3(s, n, ur);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ur[a] += pi.u[a] - pj.u[a];
+        contact(p, delta, n, ur, mij, pi.r, F, T);
+    }
+    if (p.use_lub) {
+        const double dm = 2.0 * pi.d * pj.d / (pi.d + pj.d);
+        const double upr[3] = {pi.u[0] - pj.u[0], pi.u[1] - pj.u[1], pi.u[2] - pj.u[2]};
+        lubrication(p, -delta, dm, mij, n, upr, F);
+    }
+}
+
+__device__ __forceinline__ void wall_interaction(const Phys &p, const Geo &g, const PV &pi, double F[3],
+                                                 double T[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        if (g.per[a]) continue;
+        for (int side = 0; side < 2; ++side) {
+            const double dist = side == 0 ? pi.x[a] : (double)g.n[a] - pi.x[a];
+            double n[3] = {0.0, 0.0, 0.0};
+            n[a] = side == 0 ? -1.0 : 1.0;
+            const double delta = pi.r - dist;
+            if (delta > 0.0) {
+                double s[3], ur[3];
+#pragma unroll
+                for (int b = 0; b < 3; ++b) s[b] = pi.r * pi.w[b];
+                cross3(s, n, ur);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) ur[b] += pi.u[b];
+                contact(p, delta, n, ur, pi.m, pi.r, F, T);
+            }
+            if (p.use_lub) lubrication(p, -delta, 2.0 * pi.d, pi.m, n, pi.u, F);
+        }
+    }
+}
+
+__device__ __forceinline__ void load_pv(const Parts &P, int64_t i, PV &v)
+{
+    const int64_t cap = P.cap;
+    v.d = P.d[i];
+    v.r = 0.5 * v.d;
+    v.m = P.rho[i] * sphere_volume(v.d);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        v.x[a] = P.x[a * cap + i];
+        v.u[a] = P.u[a * cap + i];
+        v.w[a] = P.w[a * cap + i];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
+{
+    const int64_t i = gidx();
+    const Parts &P = D.pt;
+    if (i >= P.np) return;
+    const int64_t cap = P.cap;
+    PV pi;
+    load_pv(P, i, pi);
+    double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+    // bins were built from the subcycle-start positions
+    int b[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) b[a] = clampi((int)floor(P.xstart[a * cap + i]), 0, D.g.n[a] - 1);
+    constexpr int kMaxR = 8;
+    int cx[2 * kMaxR + 1], cy[2 * kMaxR + 1], cz[2 * kMaxR + 1];
+    const int R = D.p.rbin;
+    const int mx = axis_range(b[0], R, D.g.n[0], D.g.per[0], cx, 2 * kMaxR + 1);
+    const int my = axis_range(b[1], R, D.g.n[1], D.g.per[1], cy, 2 * kMaxR + 1);
+    const int mz = axis_range(b[2], R, D.g.n[2], D.g.per[2], cz, 2 * kMaxR + 1);
+    for (int c2 = 0; c2 < mz; ++c2)
+        for (int c1 = 0; c1 < my; ++c1)
+            for (int c0 = 0; c0 < mx; ++c0) {
+                const int64_t bin = cidx(D.g, cx[c0], cy[c1], cz[c2]);
+                const int p0 = D.b.start[bin], p1 = D.b.start[bin + 1];
+                for (int t = p0; t < p1; ++t) {
+                    const int jdx = D.b.list[t];
+                    if (jdx == i) continue;
+                    PV pj;
+                    load_pv(P, jdx, pj);
+                    double dx[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        dx[a] = pj.x[a] - pi.x[a];
+                        if (D.g.per[a]) dx[a] -= D.g.n[a] * rint(dx[a] / D.g.n[a]);
+                    }
+                    pair_interaction(D.p, pi, pj, dx, F, T);
+                }
+            }
+    wall_interaction(D.p, D.g, pi, F, T);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        P.Fdem[a * cap + i] = F[a];
+        P.Tdem[a * cap + i] = T[a];
+    }
+}
+
+// semi-implicit Euler with the fluid forces frozen (Sec. 3.3); periodic wrap;
+// at the last substep of a subcycle: du_p/dt over the subcycle and bin count
+__global__ __launch_bounds__(kBlock) void k_integrate(Desc D, int last)
+{
+    const int64_t i = gidx();
+    const Parts &P = D.pt;
+    if (i >= P.np) return;
+    const int64_t cap = P.cap;
+    const double d = P.d[i];
+    const double m = P.rho[i] * sphere_volume(d);
+    const double I = m * d * d / 10.0;
+    const double dt = D.p.dt_dem;
+    double x[3];
+    int bad = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t k = a * cap + i;
+        const double u = P.u[k] + dt * (P.Fc[k] + P.Fdem[k]) / m;
+        P.u[k] = u;
+        P.w[k] = P.w[k] + dt * P.Tdem[k] / I;
+        double xa = P.x[k] + dt * u;
+        const double L = (double)D.g.n[a];
+        if (D.g.per[a]) {
+            if (xa >= L) xa -= L;
+            else if (xa < 0.0) {
+                xa += L;
+                if (xa >= L) xa = 0.0;
+            }
+        } else if (!(xa > 0.0 && xa < L)) {
+            bad |= FLAG_WALL;
+        }
+        if (!isfinite(xa) || !isfinite(u)) bad |= FLAG_NONFINITE;
+        P.x[k] = xa;
+        x[a] = xa;
+        double dx = xa - P.xstart[k];
+        if (D.g.per[a]) dx -= L * rint(dx / L);
+        if (fabs(dx) > D.p.skin) bad |= FLAG_SKIN;
+        if (last) P.a[k] = (u - P.ustart[k]) / D.p.dt_int;
+    }
+    if (bad) atomicOr(D.flags, bad);
+    if (last) atomicAdd(&D.b.cnt[particle_cell(D.g, x[0], x[1], x[2])], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_count(Desc D)
+{
+    const int64_t i = gidx();
+    const Parts &P = D.pt;
+    if (i >= P.np) return;
+    const int64_t cap = P.cap;
+    atomicAdd(&D.b.cnt[particle_cell(D.g, P.x[i], P.x[cap + i], P.x[2 * cap + i])], 1);
+}
+
+// exclusive scan of cnt into start (block level); resets cnt
+__global__ __launch_bounds__(kBlock) void k_scan_block(Desc D)
+{
+    __shared__ int sh[kBlock];
+    const int64_t nc = D.g.nc;
+    const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int tot = 0;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        const int64_t c = base + t;
+        v[t] = c < nc ? D.b.cnt[c] : 0;
+        tot += v[t];
+    }
+    sh[threadIdx.x] = tot;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const int add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int run = sh[threadIdx.x] - tot;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        const int64_t c = base + t;
+        if (c < nc) {
+            D.b.start[c] = run;
+            D.b.cnt[c] = 0;
+        }
+        run += v[t];
+    }
+    if (threadIdx.x == kBlock - 1) D.b.bsum[blockIdx.x] = sh[kBlock - 1];
+}
+
+// exclusive scan of the block sums, one block of 1024 threads
+__global__ __launch_bounds__(1024) void k_scan_top(int *bsum, int nb, int *total)
+{
+    __shared__ int sh[1024];
+    const int per = (nb + 1023) / 1024;
+    const int b0 = threadIdx.x * per;
+    int tot = 0;
+    for (int t = 0; t < per; ++t)
+        if (b0 + t < nb) tot += bsum[b0 + t];
+    sh[threadIdx.x] = tot;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int run = sh[threadIdx.x] - tot;
+    for (int t = 0; t < per; ++t)
+        if (b0 + t < nb) {
+            const int v = bsum[b0 + t];
+            bsum[b0 + t] = run;
+            run += v;
+        }
+    if (threadIdx.x == 1023) *total = sh[1023];
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_add(Desc D)
+{
+    const int64_t nc = D.g.nc;
+    const int64_t c = gidx();
+    if (c < nc) D.b.start[c] += D.b.bsum[c / kScanPerBlock];
+}
+
+__global__ __launch_bounds__(kBlock) void k_place(Desc D)
+{
+    const int64_t i = gidx();
+    const Parts &P = D.pt;
+    if (i >= P.np) return;
+    const int64_t cap = P.cap;
+    const int64_t c = particle_cell(D.g, P.x[i], P.x[cap + i], P.x[2 * cap + i]);
+    const int pos = D.b.start[c] + atomicAdd(&D.b.cnt[c], 1);
+    D.b.list[pos] = (int)i;
+}
+
+// order each bin by particle index (deterministic sums) and reset the counts
+__global__ __launch_bounds__(kBlock) void k_cellsort(Desc D)
+{
+    const int64_t nc = D.g.nc;
+    const int64_t c = gidx();
+    if (c >= nc) return;
+    const int p0 = D.b.start[c], p1 = D.b.start[c + 1];
+    for (int a = p0 + 1; a < p1; ++a) {
+        const int v = D.b.list[a];
+        int b = a - 1;
+        while (b >= p0 && D.b.list[b] > v) {
+            D.b.list[b + 1] = D.b.list[b];
+            --b;
+        }
+        D.b.list[b + 1] = v;
+    }
+    D.b.cnt[c] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// a10: fused GNS-LBM collide + stream (Eq. LBM_Equation, Eq. LBM_EQ,
+// Eq. Forcing, Eq. MacVel), push form: reads the post-stream PDFs of its own
+// cell, writes the post-collision values to x + c_q. Links leaving through a
+// wall reflect in place into the opposite direction (half-way bounce-back).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_stream_collide(Desc D, Cells<R> C)
+{
+    const int64_t nc = D.g.nc;
+    const int64_t c = gidx();
+    if (c == 0) *D.stepc += 1;
+    if (c >= nc) return;
+    int i, j, k;
+    cell_coords(D.g, c, i, j, k);
+    R f[19];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) f[q] = C.df_src[q * nc + c];
+    R r = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        r += f[q];
+        if (CX(q) > 0) jx += f[q]; else if (CX(q) < 0) jx -= f[q];
+        if (CY(q) > 0) jy += f[q]; else if (CY(q) < 0) jy -= f[q];
+        if (CZ(q) > 0) jz += f[q]; else if (CZ(q) < 0) jz -= f[q];
+    }
+    const R one = (R)1;
+    const R rho = one + r;
+    const R fx = C.facc[c], fy = C.facc[nc + c], fz = C.facc[2 * nc + c];
+    const R half = (R)0.5;
+    const R ux = (jx + half * fx) / rho, uy = (jy + half * fy) / rho, uz = (jz + half * fz) / rho;
+    const R eps = one - C.epsp[c];
+    const R ieps = one / eps;
+    const R uu = ux * ux + uy * uy + uz * uz;
+    const R om = (R)D.p.omega;
+    const R pre = (R)(1.0 - 0.5 / D.p.tau);
+    const bool wall_x = !D.g.per[0], wall_y = !D.g.per[1], wall_z = !D.g.per[2];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+        const R cu = (R)CX(q) * ux + (R)CY(q) * uy + (R)CZ(q) * uz;
+        const R w = (R)WQ(q);
+        const R feq = w * r + w * rho * ((R)3 * cu + (R)4.5 * cu * cu * ieps - (R)1.5 * uu * ieps);
+        const R gx = (R)3 * (R)CX(q) - (R)3 * ux * ieps + (R)9 * cu * (R)CX(q) * ieps;
+        const R gy = (R)3 * (R)CY(q) - (R)3 * uy * ieps + (R)9 * cu * (R)CY(q) * ieps;
+        const R gz = (R)3 * (R)CZ(q) - (R)3 * uz * ieps + (R)9 * cu * (R)CZ(q) * ieps;
+        const R F = w * pre * (gx * fx + gy * fy + gz * fz);
+        const R post = f[q] + (feq - f[q]) * om + F;
+        int t0 = i + CX(q), t1 = j + CY(q), t2 = k + CZ(q);
+        bool wall = false;
+        if (CX(q) != 0 && (t0 < 0 || t0 >= D.g.n[0])) {
+            if (wall_x) wall = true; else t0 = t0 < 0 ? t0 + D.g.n[0] : t0 - D.g.n[0];
+        }
+        if (CY(q) != 0 && (t1 < 0 || t1 >= D.g.n[1])) {
+            if (wall_y) wall = true; else t1 = t1 < 0 ? t1 + D.g.n[1] : t1 - D.g.n[1];
+        }
+        if (CZ(q) != 0 && (t2 < 0 || t2 >= D.g.n[2])) {
+            if (wall_z) wall = true; else t2 = t2 < 0 ? t2 + D.g.n[2] : t2 - D.g.n[2];
+        }
+        if (wall) C.df_dst[OPP(q) * nc + c] = post;
+        else C.df_dst[q * nc + cidx(D.g, t0, t1, t2)] = post;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reductions for the diagnostics (two passes, fixed order: deterministic)
+// per-block partials: [0] sum drho, [1..3] sum j, [4] sum eps, [5] min eps,
+// [6] sum u_f,z, [7] max |u_bar|, [8..10] sum m u, [11] sum u_z
+// ---------------------------------------------------------------------------
+constexpr int kDiag = 12;
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_diag(Desc D, Cells<R> C, const R *df, double *part)
+{
+    __shared__ double sh[kDiag][kBlock];
+    const int64_t nc = D.g.nc, np = D.pt.np, cap = D.pt.cap;
+    double acc[kDiag] = {0, 0, 0, 0, 0, 1e300, 0, 0, 0, 0, 0, 0};
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t c = gidx(); c < nc; c += stride) {
+        double r = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            const double f = (double)df[q * nc + c];
+            r += f;
+            jx += CX(q) * f;
+            jy += CY(q) * f;
+            jz += CZ(q) * f;
+        }
+        const double e = 1.0 - (double)C.epsp[c];
+        const double rho = 1.0 + r;
+        const double ub0 = (jx + 0.5 * e * D.p.fb[0]) / rho;
+        const double ub1 = (jy + 0.5 * e * D.p.fb[1]) / rho;
+        const double ub2 = (jz + 0.5 * e * D.p.fb[2]) / rho;
+        acc[0] += r;
+        acc[1] += jx;
+        acc[2] += jy;
+        acc[3] += jz;
+        acc[4] += e;
+        acc[5] = fmin(acc[5], e);
+        acc[6] += ub2 / e;
+        acc[7] = fmax(acc[7], sqrt(ub0 * ub0 + ub1 * ub1 + ub2 * ub2));
+    }
+    for (int64_t i = gidx(); i < np; i += stride) {
+        const double m = D.pt.rho[i] * sphere_volume(D.pt.d[i]);
+        acc[8] += m * D.pt.u[i];
+        acc[9] += m * D.pt.u[cap + i];
+        acc[10] += m * D.pt.u[2 * cap + i];
+        acc[11] += D.pt.u[2 * cap + i];
+    }
+#pragma unroll
+    for (int t = 0; t < kDiag; ++t) sh[t][threadIdx.x] = acc[t];
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < (unsigned)off) {
+#pragma unroll
+            for (int t = 0; t < kDiag; ++t) {
+                const double a = sh[t][threadIdx.x], b = sh[t][threadIdx.x + off];
+                sh[t][threadIdx.x] = t == 5 ? fmin(a, b) : (t == 7 ? fmax(a, b) : a + b);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < kDiag) part[(int64_t)blockIdx.x * kDiag + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_diag_final(const double *part, int nblk, double *out)
+{
+    const int t = threadIdx.x;
+    if (t >= kDiag) return;
+    double a = t == 5 ? 1e300 : 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        const double v = part[(int64_t)b * kDiag + t];
+        a = t == 5 ? fmin(a, v) : (t == 7 ? fmax(a, v) : a + v);
+    }
+    out[t] = a;
+}
+
+template <typename R>
+__global__ void k_zero(R *p, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = (R)0;
+}
+
+template <typename A, typename B>
+__global__ void k_convert(const A *src, B *dst, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (B)src[i];
+}
+
+__global__ void k_set_step(long long *s, long long v) { *s = v; }
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned nblocks(int64_t n, int64_t per = kBlock)
+{
+    return (unsigned)((n + per - 1) / per);
+}
+static inline unsigned grid_stride_blocks(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+template <typename R> void launch_moments(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_moments<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+}
+template <typename R> void launch_cellfields(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cellfields<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+}
+template <typename R> void launch_part_am(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    if (D.pt.np > 0) hipLaunchKernelGGL(k_part_am<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
+}
+template <typename R> void launch_gather_am(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_am<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+}
+template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    if (D.pt.np > 0) hipLaunchKernelGGL(k_part_drag<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
+}
+template <typename R> void launch_gather_fd(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_fd<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+}
+template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_eps<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+}
+template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stream_collide<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+}
+template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_zero<R>, dim3(grid_stride_blocks(n)), dim3(kBlock), 0, s, p, n);
+}
+template <typename R> void launch_to_double(const R *src, double *dst, int64_t n, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL((k_convert<R, double>), dim3(grid_stride_blocks(n)), dim3(kBlock), 0, s, src, dst, n);
+}
+template <typename R> void launch_from_double(const double *src, R *dst, int64_t n, hipStream_t s)
+{
+    if (n > 0)
+        hipLaunchKernelGGL((k_convert<double, R>), dim3(grid_stride_blocks(n)), dim3(kBlock), 0, s, src, dst, n);
+}
+int diag_blocks(const Desc &D)
+{
+    int64_t n = D.g.nc > D.pt.np ? D.g.nc : D.pt.np;
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b > 1024) b = 1024;
+    return (int)(b < 1 ? 1 : b);
+}
+template <typename R>
+void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials, int nblk, double *out,
+                 hipStream_t s)
+{
+    hipLaunchKernelGGL(k_diag<R>, dim3(nblk), dim3(kBlock), 0, s, D, C, df, partials);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, (const double *)partials, nblk, out);
+}
+
+void launch_dem_force(const Desc &D, hipStream_t s)
+{
+    if (D.pt.np > 0) hipLaunchKernelGGL(k_dem_force, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+}
+void launch_integrate(const Desc &D, int last, hipStream_t s)
+{
+    if (D.pt.np > 0) hipLaunchKernelGGL(k_integrate, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, last);
+}
+void launch_bin_count(const Desc &D, hipStream_t s)
+{
+    if (D.pt.np > 0) hipLaunchKernelGGL(k_bin_count, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+}
+void launch_bin_build(const Desc &D, hipStream_t s)
+{
+    const unsigned nb = nblocks(D.g.nc, kScanPerBlock);
+    hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kBlock), 0, s, D);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, D.b.bsum, (int)nb, D.b.start + D.g.nc);
+    hipLaunchKernelGGL(k_scan_add, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D);
+    if (D.pt.np > 0) hipLaunchKernelGGL(k_place, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+    hipLaunchKernelGGL(k_cellsort, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D);
+}
+void launch_zero_int(int *p, int64_t n, hipStream_t s) { launch_zero<int>(p, n, s); }
+void launch_set_step(long long *stepc, long long v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, stepc, v);
+}
+
+#define LBDEM_INST(R)                                                                                     \
+    template void launch_moments<R>(const Desc &, const Cells<R> &, hipStream_t);                          \
+    template void launch_cellfields<R>(const Desc &, const Cells<R> &, hipStream_t);                       \
+    template void launch_part_am<R>(const Desc &, const Cells<R> &, hipStream_t);                          \
+    template void launch_gather_am<R>(const Desc &, const Cells<R> &, hipStream_t);                        \
+    template void launch_part_drag<R>(const Desc &, const Cells<R> &, hipStream_t);                        \
+    template void launch_gather_fd<R>(const Desc &, const Cells<R> &, hipStream_t);                        \
+    template void launch_gather_eps<R>(const Desc &, const Cells<R> &, hipStream_t);                       \
+    template void launch_stream_collide<R>(const Desc &, const Cells<R> &, hipStream_t);                   \
+    template void launch_zero<R>(R *, int64_t, hipStream_t);                                                \
+    template void launch_to_double<R>(const R *, double *, int64_t, hipStream_t);                          \
+    template void launch_from_double<R>(const double *, R *, int64_t, hipStream_t);                        \
+    template void launch_diag<R>(const Desc &, const Cells<R> &, const R *, double *, int, double *, hipStream_t);
+
+LBDEM_INST(float)
+LBDEM_INST(double)
+
+}  // namespace lbdem

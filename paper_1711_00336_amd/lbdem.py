@@ -1,0 +1,255 @@
+"""ctypes binding of the C ABI in include/lbdem.h (argument marshalling only).
+
+Every step of the coupled LBM-DEM time step runs in the HIP library
+(_lib/liblbdem.so). Importing this module loads that library and raises if it
+is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "liblbdem.so")
+
+OK, E_INVALID, E_OOM, E_UNSTABLE, E_DEVICE, E_BUSY, E_STATE = range(7)
+FP64, FP32_DEV = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+FIELD_DRHO, FIELD_J, FIELD_EPS_F, FIELD_F_ACC, FIELD_DUDT, FIELD_GRADP, FIELD_UPREV, FIELD_PDF = range(8)
+FIELD_NCOMP = {FIELD_DRHO: 1, FIELD_J: 3, FIELD_EPS_F: 1, FIELD_F_ACC: 3, FIELD_DUDT: 3,
+               FIELD_GRADP: 3, FIELD_UPREV: 3, FIELD_PDF: 19}
+KCLASS = {"stream_collide": 0, "moments": 1, "cellfields": 2, "particles": 3, "gathers": 4,
+          "dem": 5, "bins": 6}
+
+
+class LbdemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lbdem status {status}: {msg}")
+        self.status = status
+
+
+class lbdem_params(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("periodic", C.c_int32 * 3),
+                ("tau", C.c_double), ("rho_f", C.c_double),
+                ("gravity", C.c_double * 3), ("body_force", C.c_double * 3),
+                ("body_force_auto", C.c_int32),
+                ("e_n", C.c_double), ("mu_c", C.c_double), ("T_c", C.c_double),
+                ("h_c", C.c_double), ("h_min", C.c_double),
+                ("lub_stab", C.c_int32), ("use_lub", C.c_int32), ("use_am", C.c_int32),
+                ("n_int", C.c_int32), ("n_dem", C.c_int32),
+                ("c_am", C.c_double), ("precision", C.c_int32), ("flags", C.c_uint32)]
+
+
+class lbdem_diag(C.Structure):
+    _fields_ = [("mass_dev", C.c_double), ("mom_fluid", C.c_double * 3),
+                ("mom_part", C.c_double * 3), ("u_ps", C.c_double),
+                ("mean_eps_f", C.c_double), ("min_eps_f", C.c_double),
+                ("max_u", C.c_double), ("step", C.c_int64), ("np", C.c_int64)]
+
+
+class lbdem_state_view(C.Structure):
+    _fields_ = [("df", C.c_void_p), ("uprev", C.c_void_p), ("step", C.c_int64),
+                ("np", C.c_int64), ("x", C.c_void_p), ("u", C.c_void_p),
+                ("omega", C.c_void_p), ("accel", C.c_void_p), ("d", C.c_void_p),
+                ("rho_p", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library not built: {LIB_PATH} (run python -m paper_1711_00336_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        H = C.c_void_p
+        st = C.c_int
+        sig = {
+            "lbdem_last_error": (C.c_char_p, [H]),
+            "lbdem_params_default": (st, [C.POINTER(lbdem_params)]),
+            "lbdem_set_allocator": (st, [C.c_void_p, C.c_void_p, C.c_void_p]),
+            "lbdem_create": (st, [C.POINTER(lbdem_params), C.c_void_p, C.POINTER(H)]),
+            "lbdem_destroy": (st, [H]),
+            "lbdem_add_particles": (st, [H, C.c_int64] + [C.c_void_p] * 5),
+            "lbdem_step": (st, [H, C.c_int64]),
+            "lbdem_sync": (st, [H]),
+            "lbdem_read_field": (st, [H, C.c_int, C.c_int, C.c_void_p]),
+            "lbdem_read_particles": (st, [H, C.c_int] + [C.c_void_p] * 4),
+            "lbdem_read_particle_forces": (st, [H] + [C.c_void_p] * 4),
+            "lbdem_diagnostics": (st, [H, C.POINTER(lbdem_diag)]),
+            "lbdem_num_cells": (C.c_int64, [H]),
+            "lbdem_num_particles": (C.c_int64, [H]),
+            "lbdem_get_state": (st, [H, C.POINTER(lbdem_state_view)]),
+            "lbdem_set_state": (st, [H, C.POINTER(lbdem_state_view)]),
+            "lbdem_save_state": (st, [H, C.c_void_p, C.POINTER(C.c_size_t)]),
+            "lbdem_load_state": (st, [H, C.c_void_p, C.c_size_t]),
+            "lbdem_set_timing": (st, [H, C.c_int]),
+            "lbdem_kernel_time": (st, [H, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _check(h, status):
+    if status != OK:
+        msg = lib().lbdem_last_error(h)
+        raise LbdemError(status, msg.decode() if msg else "")
+
+
+def params_from(prm) -> lbdem_params:
+    """lbdem_params from an inputs.Params (or any object with the same fields)."""
+    P = lbdem_params()
+    _check(None, lib().lbdem_params_default(C.byref(P)))
+    P.n[:] = [int(v) for v in prm.n]
+    P.periodic[:] = [int(v) for v in prm.periodic]
+    P.tau, P.rho_f = prm.tau, prm.rho_f
+    P.gravity[:] = list(prm.gravity)
+    P.body_force[:] = list(prm.body_force)
+    P.body_force_auto = int(prm.body_force_auto)
+    P.e_n, P.mu_c, P.T_c, P.h_c, P.h_min = prm.e_n, prm.mu_c, prm.T_c, prm.h_c, prm.h_min
+    P.lub_stab, P.use_lub, P.use_am = int(prm.lub_stab), int(prm.use_lub), int(prm.use_am)
+    P.n_int, P.n_dem = int(prm.n_int), int(prm.n_dem)
+    P.c_am = prm.c_am
+    P.precision = FP32_DEV if prm.precision == "fp32dev" else FP64
+    return P
+
+
+class Domain:
+    """One domain of the C library (lbdem_create ... lbdem_destroy)."""
+
+    def __init__(self, prm, stream=None):
+        self.prm = prm
+        self.P = params_from(prm)
+        self.h = C.c_void_p()
+        s = None if stream is None else C.c_void_p(int(stream))
+        _check(None, lib().lbdem_create(C.byref(self.P), s, C.byref(self.h)))
+        self.nc = int(lib().lbdem_num_cells(self.h))
+
+    def close(self):
+        if self.h:
+            lib().lbdem_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- calls with the names of the C ABI ----------------------------------
+    def lbdem_add_particles(self, x, u, omega, d, rho_p):
+        x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+        n = len(x)
+        u = np.ascontiguousarray(u, np.float64).reshape(n, 3)
+        omega = np.ascontiguousarray(omega, np.float64).reshape(n, 3)
+        d = np.ascontiguousarray(d, np.float64).reshape(n)
+        rho_p = np.ascontiguousarray(rho_p, np.float64).reshape(n)
+        _check(self.h, lib().lbdem_add_particles(self.h, n, _ptr(x), _ptr(u), _ptr(omega), _ptr(d), _ptr(rho_p)))
+
+    def add(self, particles):
+        self.lbdem_add_particles(particles.x, particles.u, particles.w, particles.d, particles.rho_p)
+
+    def lbdem_step(self, nsteps=1):
+        _check(self.h, lib().lbdem_step(self.h, int(nsteps)))
+
+    def lbdem_sync(self):
+        _check(self.h, lib().lbdem_sync(self.h))
+
+    def step(self, nsteps=1, sync=True):
+        self.lbdem_step(nsteps)
+        if sync:
+            self.lbdem_sync()
+
+    def lbdem_read_field(self, field, out=None):
+        ncomp = FIELD_NCOMP[field]
+        if out is None:
+            out = np.zeros((ncomp, self.nc) if ncomp > 1 else (self.nc,))
+            _check(self.h, lib().lbdem_read_field(self.h, field, MEM_HOST, _ptr(out)))
+        else:  # torch tensor on the device
+            _check(self.h, lib().lbdem_read_field(self.h, field, MEM_DEVICE, C.c_void_p(out.data_ptr())))
+        return out
+
+    def num_particles(self):
+        return int(lib().lbdem_num_particles(self.h))
+
+    def lbdem_read_particles(self):
+        n = self.num_particles()
+        x, u, w, a = (np.zeros((n, 3)) for _ in range(4))
+        _check(self.h, lib().lbdem_read_particles(self.h, MEM_HOST, _ptr(x), _ptr(u), _ptr(w), _ptr(a)))
+        return x, u, w, a
+
+    def lbdem_read_particle_forces(self):
+        n = self.num_particles()
+        F = [np.zeros((n, 3)) for _ in range(4)]
+        _check(self.h, lib().lbdem_read_particle_forces(self.h, *[_ptr(f) for f in F]))
+        return dict(F_am=F[0], F_d=F[1], F_pr=F[2], F_const=F[3])
+
+    def lbdem_diagnostics(self):
+        D = lbdem_diag()
+        _check(self.h, lib().lbdem_diagnostics(self.h, C.byref(D)))
+        return dict(mass_dev=D.mass_dev, mom_fluid=np.array(D.mom_fluid[:]), mom_part=np.array(D.mom_part[:]),
+                    u_ps=D.u_ps, mean_eps_f=D.mean_eps_f, min_eps_f=D.min_eps_f, max_u=D.max_u,
+                    step=D.step, np=D.np)
+
+    def lbdem_get_state(self):
+        n = self.num_particles()
+        df = np.zeros((19, self.nc)); up = np.zeros((3, self.nc))
+        x, u, w, a = (np.zeros((n, 3)) for _ in range(4))
+        d = np.zeros(n); r = np.zeros(n)
+        V = lbdem_state_view(_ptr(df).value, _ptr(up).value, 0, n, _ptr(x).value, _ptr(u).value,
+                             _ptr(w).value, _ptr(a).value, _ptr(d).value, _ptr(r).value)
+        _check(self.h, lib().lbdem_get_state(self.h, C.byref(V)))
+        return dict(df=df, uprev=up, step=int(V.step), x=x, u=u, w=w, a=a, d=d, rho_p=r)
+
+    def lbdem_set_state(self, df, uprev, step, x, u, w, a, d, rho_p):
+        arrs = [np.ascontiguousarray(v, np.float64) for v in (df, uprev, x, u, w, a, d, rho_p)]
+        n = len(arrs[6])
+        assert arrs[0].size == 19 * self.nc and arrs[1].size == 3 * self.nc
+        V = lbdem_state_view(_ptr(arrs[0]).value, _ptr(arrs[1]).value, int(step), n,
+                             *[_ptr(v).value for v in arrs[2:]])
+        _check(self.h, lib().lbdem_set_state(self.h, C.byref(V)))
+
+    def lbdem_save_state(self) -> bytes:
+        sz = C.c_size_t(0)
+        _check(self.h, lib().lbdem_save_state(self.h, None, C.byref(sz)))
+        buf = (C.c_char * sz.value)()
+        _check(self.h, lib().lbdem_save_state(self.h, C.cast(buf, C.c_void_p), C.byref(sz)))
+        return bytes(buf)
+
+    def lbdem_load_state(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(self.h, lib().lbdem_load_state(self.h, C.cast(buf, C.c_void_p), len(blob)))
+
+    def lbdem_set_timing(self, on: bool):
+        _check(self.h, lib().lbdem_set_timing(self.h, 1 if on else 0))
+
+    def lbdem_kernel_time(self, cls):
+        ms = C.c_double(0.0); n = C.c_int64(0)
+        c = KCLASS[cls] if isinstance(cls, str) else int(cls)
+        _check(self.h, lib().lbdem_kernel_time(self.h, c, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+
+def exported_symbols():
+    """Names declared in include/lbdem.h (for the export test)."""
+    import re
+    hdr = os.path.join(os.path.dirname(_HERE), "include", "lbdem.h")
+    src = open(hdr).read()
+    return sorted(set(re.findall(r"\b(lbdem_[a-z_]+)\s*\(", src)))

@@ -1,0 +1,185 @@
+"""GPU (HIP, through the C ABI) vs FP64 oracle: one coupled step from an
+identical state, compared array by array.
+
+Bar (FP64 path): max|X_gpu - X_oracle| <= 1e-12 * max|X_oracle| for the PDF
+deviations, u_prev, particle positions (minimum image), velocities and
+angular velocities after one step; the subcycle acceleration du_p/dt, a
+difference quotient, is measured against max(|a|, n_int max|u|).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1711_00336_amd import inputs as I
+from tests.parity_util import compare_states, load_oracle_state, warm_oracle, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1711_00336_amd import lbdem
+    lbdem.lib()
+    return lbdem
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _one_step_parity(L, case, warm, nsteps=2, tol=TOL64, perturb=None):
+    _say(f"case {case.name} seed {case.seed} n {case.params.n} np {case.particles.n}")
+    o = warm_oracle(case, warm, perturb)
+    dom = L.Domain(case.params)
+    worst = {}
+    try:
+        for s in range(nsteps):
+            load_oracle_state(dom, o.state)
+            dom.step(1)
+            r = o.step(1)
+            assert r["status"] == 0
+            g = dom.lbdem_get_state()
+            errs, bad = compare_states(g, o.state, case.params, tol)
+            for k, v in errs.items():
+                worst[k] = max(worst.get(k, 0.0), v)
+            assert not bad, (s, errs)
+    finally:
+        dom.close()
+    _say(f"  worst rel errors {worst}")
+    return worst
+
+
+def test_parity_walled_64_spheres(L):
+    """32x32x64 walled domain, 64 spheres d=0.5, FP64 (the small workload)."""
+    case = I.case_small_walled(0)
+    _one_step_parity(L, case, warm=3, nsteps=3)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_parity_walled_64_spheres_seeds(L, seed):
+    case = I.case_small_walled(seed)
+    _one_step_parity(L, case, warm=2, nsteps=2)
+
+
+def test_parity_pure_fluid_ragged_perturbed(L):
+    """No particles, ragged sizes (several 256-cell blocks plus a tail), walls on
+    two axes, random PDF deviations and a body force."""
+    prm = I.Params(n=(37, 29, 23), periodic=(1, 0, 0), tau=0.73, body_force=(2e-6, -1e-6, 3e-6),
+                   n_int=2, precision="fp64")
+    empty = I.Particles(np.zeros((0, 3)), np.zeros((0, 3)), np.zeros((0, 3)), np.zeros(0), np.zeros(0))
+    case = I.Case("pure-fluid-ragged", prm, empty, 0)
+    nc = 37 * 29 * 23
+    _one_step_parity(L, case, warm=0, nsteps=2, perturb=I.perturbed_state(3, nc, 1e-4))
+
+
+def test_parity_dense_contacts_lubrication(L):
+    """Dense polydisperse packing with random velocities: contacts, friction,
+    lubrication (with the stability floor) and walls all active."""
+    prm = I.Params(n=(14, 12, 16), periodic=(1, 1, 0), tau=0.7, gravity=(0, 0, -1e-5), e_n=0.9,
+                   mu_c=0.25, T_c=0.0, h_c=1.0, n_int=3, n_dem=4, precision="fp64")
+    parts = I.make_particles(4, prm, 0.35, 0.9, 1.1, 2.5)
+    rng = np.random.default_rng(11)
+    parts.u[:] = rng.normal(size=parts.u.shape) * 2e-3
+    parts.w[:] = rng.normal(size=parts.w.shape) * 2e-3
+    case = I.Case("dense-contacts", prm, parts, 4)
+    _one_step_parity(L, case, warm=2, nsteps=2)
+
+
+def test_parity_periodic_settling_ragged(L):
+    """Fully periodic settling box with a balancing body force, 0.1 solid
+    fraction, ragged edge."""
+    case = I.case_settling(5, 21, 0.1, 0.8, 2.5, precision="fp64")
+    _one_step_parity(L, case, warm=3, nsteps=2)
+
+
+def test_parity_degenerate_thin_periodic_axis(L):
+    """A periodic axis of 2 cells: kernel stencils and neighbour bins wrap onto
+    themselves."""
+    prm = I.Params(n=(2, 9, 10), periodic=(1, 1, 0), tau=0.9, gravity=(0, 0, -1e-5), h_c=0.5,
+                   n_int=2, precision="fp64")
+    parts = I.make_particles(6, prm, 6, 0.5, 0.5, 2.0)
+    case = I.Case("thin-axis", prm, parts, 6)
+    _one_step_parity(L, case, warm=2, nsteps=2)
+
+
+def test_rest_state_stays_exactly_at_rest(L):
+    prm = I.Params(n=(33, 17, 9), periodic=(1, 1, 0), precision="fp64")
+    with L.Domain(prm) as dom:
+        dom.step(3)
+        g = dom.lbdem_get_state()
+        assert np.all(g["df"] == 0.0)
+
+
+def test_mass_conservation_and_determinism(L):
+    case = I.case_small_walled(3)
+    runs = []
+    for _ in range(2):
+        with L.Domain(case.params) as dom:
+            dom.add(case.particles)
+            d0 = dom.lbdem_diagnostics()
+            dom.step(20)
+            d1 = dom.lbdem_diagnostics()
+            assert abs(d1["mass_dev"] - d0["mass_dev"]) < 1e-12
+            runs.append(dom.lbdem_get_state())
+    for k in ("df", "uprev", "x", "u", "w", "a"):
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+
+
+def test_checkpoint_roundtrip_bitwise(L):
+    case = I.case_small_walled(4)
+    with L.Domain(case.params) as a:
+        a.add(case.particles)
+        a.step(4)
+        blob = a.lbdem_save_state()
+        a.step(4)
+        ga = a.lbdem_get_state()
+    with L.Domain(case.params) as b:
+        b.lbdem_load_state(blob)
+        b.step(4)
+        gb = b.lbdem_get_state()
+    for k in ("df", "uprev", "x", "u", "w", "a"):
+        assert np.array_equal(ga[k], gb[k]), k
+    assert ga["step"] == gb["step"] == 8
+
+
+def test_diagnostics_match_oracle(L):
+    from oracle import oracle as O
+    case = I.case_settling(8, 16, 0.1, 0.8, 2.5, precision="fp64")
+    o = warm_oracle(case, 2)
+    with L.Domain(case.params) as dom:
+        load_oracle_state(dom, o.state)
+        dg = dom.lbdem_diagnostics()
+    do = o.diagnostics()
+    assert abs(dg["mass_dev"] - do["mass_dev"]) < 1e-12
+    assert rel_err(dg["mom_fluid"], do["mom_fluid"]) < 1e-10
+    assert rel_err(dg["mom_part"], do["mom_part"]) < 1e-12
+    assert dg["u_ps"] == pytest.approx(do["u_ps"], rel=1e-10)
+    assert dg["mean_eps_f"] == pytest.approx(do["mean_eps_f"], rel=1e-14)
+    assert dg["min_eps_f"] == pytest.approx(do["min_eps_f"], rel=1e-14)
+
+
+def test_unstable_flag_on_skin_violation(L):
+    """A particle moving several cells per subcycle is reported as unstable
+    (host-forced condition; every kernel exits normally)."""
+    prm = I.Params(n=(16, 16, 16), periodic=(1, 1, 1), precision="fp64", n_int=1)
+    with L.Domain(prm) as dom:
+        dom.lbdem_add_particles(np.array([[8.2, 8.3, 8.4]]), np.array([[0.5, 0.0, 0.0]]),
+                                np.zeros((1, 3)), np.array([0.5]), np.array([2.5]))
+        dom.lbdem_step(1)
+        with pytest.raises(L.LbdemError) as e:
+            dom.lbdem_sync()
+        assert e.value.status == L.E_UNSTABLE
+
+
+def test_add_particles_rejects_bad_input(L):
+    prm = I.Params(n=(8, 8, 8), periodic=(1, 1, 0), precision="fp64")
+    with L.Domain(prm) as dom:
+        for x, d in (([[1.0, 1.0, 9.0]], 0.5), ([[1.0, 1.0, 4.0]], -1.0), ([[np.nan, 1.0, 4.0]], 0.5)):
+            with pytest.raises(L.LbdemError) as e:
+                dom.lbdem_add_particles(np.array(x), np.zeros((1, 3)), np.zeros((1, 3)), np.array([d]),
+                                        np.array([2.0]))
+            assert e.value.status == L.E_INVALID
+        assert dom.num_particles() == 0
