@@ -85,8 +85,12 @@ typedef struct lbdem_params {
     int32_t precision;       /* LBDEM_FP64 or LBDEM_FP32_DEV (PDFs and cell fields
                                 as FP32 deviations from the rest weights; particle
                                 integration and reductions stay FP64) */
-    uint32_t flags;          /* reserved, 0 */
+    uint32_t flags;          /* LBDEM_FLAG_* bits, 0 by default */
 } lbdem_params;
+
+/* lbdem_params.flags: launch every kernel of a step directly instead of
+ * replaying a captured HIP graph (same results, for debugging/profiling). */
+#define LBDEM_FLAG_NO_GRAPH 1u
 
 typedef struct lbdem_diag {
     double mass_dev;         /* sum_x (rho - 1) */
@@ -138,7 +142,8 @@ lbdem_status lbdem_destroy(lbdem_domain_t h);
 /* Append n spheres (Sec. 3.1): host arrays x,u,omega [n][3], d,rho_p [n].
  * Copied synchronously; the fluid volume fraction (Eq. fluid_volume_fraction)
  * and an automatic f_b are recomputed. E_INVALID if a centre lies outside
- * the domain, a sphere crosses a wall, d <= 0 or rho_p <= 0. */
+ * the domain (on [0, n) of a periodic axis, strictly inside (0, n) between
+ * walls), a value is not finite, d <= 0 or rho_p <= 0. */
 lbdem_status lbdem_add_particles(lbdem_domain_t h, int64_t n, const double *x, const double *u,
                                  const double *omega, const double *d, const double *rho_p);
 

@@ -58,7 +58,7 @@ struct lbdem_domain {
     // cell arrays (one of the two precisions is used)
     void *df[2] = {nullptr, nullptr};
     int cur = 0;
-    void *drho = nullptr, *j = nullptr, *uprev = nullptr, *dudt = nullptr, *gradp = nullptr;
+    void *drho = nullptr, *j = nullptr, *uprev = nullptr, *un = nullptr, *dudt = nullptr, *gradp = nullptr;
     void *epsp = nullptr, *fam = nullptr, *facc = nullptr;
     // bins
     int *cnt = nullptr, *start = nullptr, *list = nullptr, *bsum = nullptr;
@@ -72,6 +72,21 @@ struct lbdem_domain {
     double *diag_part = nullptr, *diag_out = nullptr, *tmp = nullptr;
     int64_t tmp_len = 0;
     std::vector<void *> owned;
+
+    // captured steps, keyed by (PDF buffer, particle buffer parity)
+    bool use_graphs = true;
+    int pswap = 0;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+
+    void drop_graphs()
+    {
+        for (auto &row : graph)
+            for (auto &g : row)
+                if (g) {
+                    (void)hipGraphExecDestroy(g);
+                    g = nullptr;
+                }
+    }
 
     // timing
     bool timing = false;
@@ -133,6 +148,7 @@ struct lbdem_domain {
         C.drho = (R *)drho;
         C.j = (R *)j;
         C.uprev = (R *)uprev;
+        C.un = (R *)un;
         C.dudt = (R *)dudt;
         C.gradp = (R *)gradp;
         C.epsp = (R *)epsp;
@@ -214,6 +230,14 @@ void harvest_timing(lbdem_domain_t h)
     h->ev_used = 0;
 }
 
+// constants for n / d = (umulhi(n, m) + n) >> s, valid for 0 <= n < 2^31
+void set_fastdiv(uint32_t d, uint32_t &m, uint32_t &s)
+{
+    s = 0;
+    while ((1ull << s) < d) ++s;
+    m = (uint32_t)((((uint64_t)1 << 32) * ((1ull << s) - d)) / d + 1);
+}
+
 void resolve_phys(lbdem_domain_t h)
 {
     const lbdem_params &p = h->prm;
@@ -238,6 +262,11 @@ void resolve_phys(lbdem_domain_t h)
     P.dt_int = 1.0 / p.n_int;
     P.dt_dem = P.dt_int / p.n_dem;
     P.T_c = p.T_c > 0.0 ? p.T_c : 20.0 * P.dt_dem;
+    // Eq. damping_to_stiffness and Eq. collision_time solved for the pair's
+    // k_n and xi_n: k_n = m_ij (pi^2 + ln^2 e_n)/T_c^2, xi_n = -2 ln(e_n) m_ij/T_c
+    const double L = std::log(p.e_n);
+    P.kn_per_m = (M_PI * M_PI + L * L) / (P.T_c * P.T_c);
+    P.xi_per_m = -2.0 * L / P.T_c;
     P.c_am = p.c_am;
     P.skin = 0.1;
     P.rbin = 1;
@@ -263,15 +292,34 @@ void update_body_force(lbdem_domain_t h, const std::vector<double> &d, const std
     for (int a = 0; a < 3; ++a) h->phys.fb[a] = all_per ? -s * p.gravity[a] : 0.0;
 }
 
+void swap_particle_buffers(lbdem_domain_t h)
+{
+    Parts &P = h->pt;
+    h->pswap ^= 1;
+    std::swap(P.x, P.x2);
+    std::swap(P.u, P.u2);
+    std::swap(P.w, P.w2);
+    std::swap(P.a, P.a2);
+    std::swap(P.d, P.d2);
+    std::swap(P.rho, P.rho2);
+    std::swap(P.id, P.id2);
+}
+
+// bins of the current positions, slots sorted into bin order, stencils
+void sort_particles(lbdem_domain_t h)
+{
+    launch_bin_build(h->desc(), h->stream);
+    launch_sort_permute(h->desc(), h->stream);
+    swap_particle_buffers(h);
+}
+
 template <typename R>
 void rebuild_particle_fields(lbdem_domain_t h)
 {
-    Desc D = h->desc();
-    Cells<R> C = h->cells<R>();
     launch_zero_int(h->cnt, h->geo.nc, h->stream);
-    launch_bin_count(D, h->stream);
-    launch_bin_build(D, h->stream);
-    launch_gather_eps<R>(D, C, h->stream);
+    launch_bin_count(h->desc(), h->stream);
+    sort_particles(h);
+    launch_gather_eps<R>(h->desc(), h->cells<R>(), h->stream);
     hip_check(hipGetLastError(), "particle field rebuild");
 }
 
@@ -285,24 +333,38 @@ void rebuild(lbdem_domain_t h)
 void alloc_particles(lbdem_domain_t h, int64_t cap)
 {
     Parts &P = h->pt;
-    double **vec[] = {&P.x, &P.u, &P.w, &P.a, &P.Fam, &P.Fd, &P.Fpr, &P.Fc, &P.Fdem, &P.Tdem, &P.ustart, &P.xstart};
-    for (double **v : vec) {
-        h->dfree(*v);
-        *v = nullptr;
-    }
-    h->dfree(P.d);
-    h->dfree(P.rho);
+    double **vec[] = {&P.x, &P.u, &P.w, &P.a, &P.x2, &P.u2, &P.w2, &P.a2, &P.Fam, &P.Fd, &P.Fpr, &P.Fc,
+                      &P.Fdem, &P.Tdem, &P.ustart, &P.xstart, &P.Fam_id, &P.Fd_id, &P.Fpr_id, &P.Fc_id};
+    double **sca[] = {&P.d, &P.rho, &P.d2, &P.rho2};
+    int **ints[] = {&P.id, &P.id2};
+    for (double **v : vec) { h->dfree(*v); *v = nullptr; }
+    for (double **v : sca) { h->dfree(*v); *v = nullptr; }
+    for (int **v : ints) { h->dfree(*v); *v = nullptr; }
+    h->dfree(P.sb);
+    h->dfree(P.sw);
     h->dfree(h->list);
-    P.d = P.rho = nullptr;
+    P.sb = nullptr;
+    P.sw = nullptr;
     h->list = nullptr;
     P.cap = std::max<int64_t>(cap, 1);
+    const size_t c = (size_t)P.cap;
     for (double **v : vec) {
-        *v = (double *)h->dalloc(sizeof(double) * 3 * (size_t)P.cap);
-        hip_check(hipMemsetAsync(*v, 0, sizeof(double) * 3 * (size_t)P.cap, h->stream), "hipMemsetAsync");
+        *v = (double *)h->dalloc(sizeof(double) * 3 * c);
+        hip_check(hipMemsetAsync(*v, 0, sizeof(double) * 3 * c, h->stream), "hipMemsetAsync");
     }
-    P.d = (double *)h->dalloc(sizeof(double) * (size_t)P.cap);
-    P.rho = (double *)h->dalloc(sizeof(double) * (size_t)P.cap);
-    h->list = (int *)h->dalloc(sizeof(int) * (size_t)P.cap);
+    for (double **v : sca) {
+        *v = (double *)h->dalloc(sizeof(double) * c);
+        hip_check(hipMemsetAsync(*v, 0, sizeof(double) * c, h->stream), "hipMemsetAsync");
+    }
+    for (int **v : ints) {
+        *v = (int *)h->dalloc(sizeof(int) * c);
+        hip_check(hipMemsetAsync(*v, 0, sizeof(int) * c, h->stream), "hipMemsetAsync");
+    }
+    P.sb = (int *)h->dalloc(sizeof(int) * 3 * c);
+    P.sw = (double *)h->dalloc(sizeof(double) * 9 * c);
+    hip_check(hipMemsetAsync(P.sb, 0, sizeof(int) * 3 * c, h->stream), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(P.sw, 0, sizeof(double) * 9 * c, h->stream), "hipMemsetAsync");
+    h->list = (int *)h->dalloc(sizeof(int) * c);
     h->list_cap = P.cap;
 }
 
@@ -335,29 +397,57 @@ struct HostParticles {
     std::vector<double> x, u, w, a, d, rho;
 };
 
+std::vector<int> fetch_ids(lbdem_domain_t h)
+{
+    std::vector<int> id(h->pt.np);
+    if (h->pt.np)
+        hip_check(hipMemcpy(id.data(), h->pt.id, sizeof(int) * h->pt.np, hipMemcpyDeviceToHost), "download");
+    return id;
+}
+
+// slot-order SoA vector -> insertion-order AoS [n][3]
+void download_vec_ordered(lbdem_domain_t h, const double *dev, double *host, const std::vector<int> &id)
+{
+    const int64_t n = (int64_t)id.size();
+    if (n == 0 || !host) return;
+    std::vector<double> tmp(3 * n);
+    download_vec(h, dev, tmp.data(), n);
+    for (int64_t s = 0; s < n; ++s)
+        for (int a = 0; a < 3; ++a) host[3 * id[s] + a] = tmp[3 * s + a];
+}
+
+void download_scalar_ordered(lbdem_domain_t h, const double *dev, double *host, const std::vector<int> &id)
+{
+    const int64_t n = (int64_t)id.size();
+    if (n == 0 || !host) return;
+    std::vector<double> tmp(n);
+    hip_check(hipMemcpy(tmp.data(), dev, sizeof(double) * n, hipMemcpyDeviceToHost), "download");
+    for (int64_t s = 0; s < n; ++s) host[id[s]] = tmp[s];
+}
+
 HostParticles fetch_particles(lbdem_domain_t h)
 {
     HostParticles hp;
     const int64_t n = h->pt.np;
+    const std::vector<int> id = fetch_ids(h);
     hp.x.resize(3 * n);
     hp.u.resize(3 * n);
     hp.w.resize(3 * n);
     hp.a.resize(3 * n);
     hp.d.resize(n);
     hp.rho.resize(n);
-    download_vec(h, h->pt.x, hp.x.data(), n);
-    download_vec(h, h->pt.u, hp.u.data(), n);
-    download_vec(h, h->pt.w, hp.w.data(), n);
-    download_vec(h, h->pt.a, hp.a.data(), n);
-    if (n) {
-        hip_check(hipMemcpy(hp.d.data(), h->pt.d, sizeof(double) * n, hipMemcpyDeviceToHost), "download");
-        hip_check(hipMemcpy(hp.rho.data(), h->pt.rho, sizeof(double) * n, hipMemcpyDeviceToHost), "download");
-    }
+    download_vec_ordered(h, h->pt.x, hp.x.data(), id);
+    download_vec_ordered(h, h->pt.u, hp.u.data(), id);
+    download_vec_ordered(h, h->pt.w, hp.w.data(), id);
+    download_vec_ordered(h, h->pt.a, hp.a.data(), id);
+    download_scalar_ordered(h, h->pt.d, hp.d.data(), id);
+    download_scalar_ordered(h, h->pt.rho, hp.rho.data(), id);
     return hp;
 }
 
 void put_particles(lbdem_domain_t h, const HostParticles &hp)
 {
+    h->drop_graphs();
     const int64_t n = (int64_t)hp.d.size();
     if (n > h->pt.cap) alloc_particles(h, std::max<int64_t>(n, 2 * h->pt.cap));
     h->pt.np = n;
@@ -368,6 +458,9 @@ void put_particles(lbdem_domain_t h, const HostParticles &hp)
     if (n) {
         hip_check(hipMemcpy(h->pt.d, hp.d.data(), sizeof(double) * n, hipMemcpyHostToDevice), "upload");
         hip_check(hipMemcpy(h->pt.rho, hp.rho.data(), sizeof(double) * n, hipMemcpyHostToDevice), "upload");
+        std::vector<int> id(n);
+        for (int64_t i = 0; i < n; ++i) id[i] = (int)i;
+        hip_check(hipMemcpy(h->pt.id, id.data(), sizeof(int) * n, hipMemcpyHostToDevice), "upload");
     }
     h->dmax = 0.0;
     for (double v : hp.d) h->dmax = std::max(h->dmax, v);
@@ -394,26 +487,63 @@ template <typename R>
 void enqueue_step(lbdem_domain_t h)
 {
     hipStream_t s = h->stream;
-    const Desc D = h->desc();
     const Cells<R> C = h->cells<R>();
-    launch_cls(h, 1, [&] { launch_moments<R>(D, C, s); });
-    launch_cls(h, 2, [&] { launch_cellfields<R>(D, C, s); });
+    launch_cls(h, 1, [&] { launch_moments<R>(h->desc(), C, s); });
+    launch_cls(h, 2, [&] { launch_cellfields<R>(h->desc(), C, s); });
     for (int k = 0; k < h->phys.n_int; ++k) {
-        launch_cls(h, 3, [&] { launch_part_am<R>(D, C, s); });
-        launch_cls(h, 4, [&] { launch_gather_am<R>(D, C, s); });
-        launch_cls(h, 3, [&] { launch_part_drag<R>(D, C, s); });
-        launch_cls(h, 4, [&] { launch_gather_fd<R>(D, C, s); });
+        const int last_sub = k == h->phys.n_int - 1;
+        launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
+        launch_cls(h, 4, [&] { launch_gather_am<R>(h->desc(), C, s); });
+        launch_cls(h, 3, [&] { launch_part_drag<R>(h->desc(), C, last_sub, s); });
+        launch_cls(h, 4, [&] { launch_gather_fd<R>(h->desc(), C, s); });
         for (int sub = 0; sub < h->phys.n_dem; ++sub) {
-            launch_cls(h, 5, [&] { launch_dem_force(D, s); });
-            launch_cls(h, 5, [&] { launch_integrate(D, sub == h->phys.n_dem - 1, s); });
+            launch_cls(h, 5, [&] { launch_dem_force(h->desc(), s); });
+            launch_cls(h, 5, [&] { launch_integrate(h->desc(), sub == h->phys.n_dem - 1, s); });
         }
-        launch_cls(h, 6, [&] { launch_bin_build(D, s); });
-        launch_cls(h, 4, [&] { launch_gather_eps<R>(D, C, s); });
+        launch_cls(h, 6, [&] { sort_particles(h); });
+        launch_cls(h, 4, [&] { launch_gather_eps<R>(h->desc(), C, s); });
     }
-    launch_cls(h, 0, [&] { launch_stream_collide<R>(D, C, s); });
+    launch_cls(h, 0, [&] { launch_stream_collide<R>(h->desc(), C, s); });
     hip_check(hipGetLastError(), "kernel launch");
     h->cur ^= 1;
     h->step_host += 1;
+}
+
+// one step, replayed from a captured graph when possible (kernel arguments,
+// including the buffer pointers of the step, are baked into the graph; the
+// host-side buffer bookkeeping is advanced exactly as a direct launch would)
+template <typename R>
+void run_step(lbdem_domain_t h)
+{
+    if (!h->use_graphs || h->timing) {
+        enqueue_step<R>(h);
+        return;
+    }
+    hipGraphExec_t &ge = h->graph[h->cur][h->pswap];
+    if (!ge) {
+        hipGraph_t g = nullptr;
+        hip_check(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        try {
+            enqueue_step<R>(h);
+        } catch (...) {
+            hipGraph_t dummy = nullptr;
+            (void)hipStreamEndCapture(h->stream, &dummy);
+            if (dummy) (void)hipGraphDestroy(dummy);
+            throw;
+        }
+        hip_check(hipStreamEndCapture(h->stream, &g), "hipStreamEndCapture");
+        // undo the bookkeeping of the capture; the launch below redoes it
+        h->cur ^= 1;
+        h->step_host -= 1;
+        if (h->phys.n_int & 1) swap_particle_buffers(h);
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        hip_check(e, "hipGraphInstantiate");
+    }
+    hip_check(hipGraphLaunch(ge, h->stream), "hipGraphLaunch");
+    h->cur ^= 1;
+    h->step_host += 1;
+    if (h->phys.n_int & 1) swap_particle_buffers(h);
 }
 
 template <typename R>
@@ -517,11 +647,14 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
     h->prm = *p;
     h->al = DevAlloc{g_alloc, g_free, g_alloc_ctx};
     h->prec = p->precision;
+    h->use_graphs = (p->flags & LBDEM_FLAG_NO_GRAPH) == 0;
     for (int a = 0; a < 3; ++a) {
         h->geo.n[a] = p->n[a];
         h->geo.per[a] = p->periodic[a] ? 1 : 0;
     }
     h->geo.nc = nc;
+    set_fastdiv((uint32_t)p->n[0], h->geo.mx, h->geo.sx);
+    set_fastdiv((uint32_t)p->n[0] * (uint32_t)p->n[1], h->geo.mxy, h->geo.sxy);
     resolve_phys(h);
     lbdem_status st = guarded(nullptr, [&]() -> lbdem_status {
         if (hip_stream) h->stream = (hipStream_t)hip_stream;
@@ -535,6 +668,7 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
         h->drho = h->dalloc(rs * nc);
         h->j = h->dalloc(rs * 3 * nc);
         h->uprev = h->dalloc(rs * 3 * nc);
+        h->un = h->dalloc(rs * 3 * nc);
         h->dudt = h->dalloc(rs * 3 * nc);
         h->gradp = h->dalloc(rs * 3 * nc);
         h->epsp = h->dalloc(rs * nc);
@@ -549,7 +683,7 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
         h->diag_out = (double *)h->dalloc(sizeof(double) * 16);
         for (void *q : {h->df[0], h->df[1]}) hip_check(hipMemsetAsync(q, 0, rs * 19 * nc, h->stream), "memset");
         for (void *q : {h->drho, h->epsp}) hip_check(hipMemsetAsync(q, 0, rs * nc, h->stream), "memset");
-        for (void *q : {h->j, h->uprev, h->dudt, h->gradp, h->fam, h->facc})
+        for (void *q : {h->j, h->uprev, h->un, h->dudt, h->gradp, h->fam, h->facc})
             hip_check(hipMemsetAsync(q, 0, rs * 3 * nc, h->stream), "memset");
         hip_check(hipMemsetAsync(h->cnt, 0, sizeof(int) * nc, h->stream), "memset");
         hip_check(hipMemsetAsync(h->start, 0, sizeof(int) * (nc + 1), h->stream), "memset");
@@ -574,6 +708,7 @@ lbdem_status lbdem_destroy(lbdem_domain_t h)
 {
     if (!h) return LBDEM_OK;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
+    h->drop_graphs();
     for (auto &e : h->ev_pool) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
@@ -616,8 +751,8 @@ lbdem_status lbdem_step(lbdem_domain_t h, int64_t nsteps)
     if (nsteps < 0) return fail(h, LBDEM_E_INVALID, "nsteps < 0");
     return guarded(h, [&]() -> lbdem_status {
         for (int64_t s = 0; s < nsteps; ++s) {
-            if (h->prec == LBDEM_FP64) enqueue_step<double>(h);
-            else enqueue_step<float>(h);
+            if (h->prec == LBDEM_FP64) run_step<double>(h);
+            else run_step<float>(h);
         }
         return LBDEM_OK;
     });
@@ -665,16 +800,17 @@ lbdem_status lbdem_read_particles(lbdem_domain_t h, int mem_kind, double *x, dou
     return guarded(h, [&]() -> lbdem_status {
         hip_check(hipStreamSynchronize(h->stream), "sync");
         const int64_t n = h->pt.np;
+        const std::vector<int> id = fetch_ids(h);
         const double *src[4] = {h->pt.x, h->pt.u, h->pt.w, h->pt.a};
         double *dst[4] = {x, u, omega, accel};
         for (int t = 0; t < 4; ++t) {
             if (!dst[t]) continue;
             if (mem_kind == LBDEM_MEM_DEVICE) {
                 std::vector<double> host(3 * n);
-                download_vec(h, src[t], host.data(), n);
+                download_vec_ordered(h, src[t], host.data(), id);
                 hip_check(hipMemcpy(dst[t], host.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice), "copy");
             } else {
-                download_vec(h, src[t], dst[t], n);
+                download_vec_ordered(h, src[t], dst[t], id);
             }
         }
         return LBDEM_OK;
@@ -687,10 +823,10 @@ lbdem_status lbdem_read_particle_forces(lbdem_domain_t h, double *F_am, double *
     return guarded(h, [&]() -> lbdem_status {
         hip_check(hipStreamSynchronize(h->stream), "sync");
         const int64_t n = h->pt.np;
-        download_vec(h, h->pt.Fam, F_am, n);
-        download_vec(h, h->pt.Fd, F_d, n);
-        download_vec(h, h->pt.Fpr, F_pr, n);
-        download_vec(h, h->pt.Fc, F_const, n);
+        download_vec(h, h->pt.Fam_id, F_am, n);
+        download_vec(h, h->pt.Fd_id, F_d, n);
+        download_vec(h, h->pt.Fpr_id, F_pr, n);
+        download_vec(h, h->pt.Fc_id, F_const, n);
         return LBDEM_OK;
     });
 }
@@ -757,13 +893,13 @@ lbdem_status lbdem_get_state(lbdem_domain_t h, lbdem_state_view *v)
         }
         v->step = h->step_host;
         v->np = h->pt.np;
-        const int64_t n = h->pt.np;
-        download_vec(h, h->pt.x, v->x, n);
-        download_vec(h, h->pt.u, v->u, n);
-        download_vec(h, h->pt.w, v->omega, n);
-        download_vec(h, h->pt.a, v->accel, n);
-        if (n && v->d) hip_check(hipMemcpy(v->d, h->pt.d, sizeof(double) * n, hipMemcpyDeviceToHost), "copy");
-        if (n && v->rho_p) hip_check(hipMemcpy(v->rho_p, h->pt.rho, sizeof(double) * n, hipMemcpyDeviceToHost), "copy");
+        const std::vector<int> id = fetch_ids(h);
+        download_vec_ordered(h, h->pt.x, v->x, id);
+        download_vec_ordered(h, h->pt.u, v->u, id);
+        download_vec_ordered(h, h->pt.w, v->omega, id);
+        download_vec_ordered(h, h->pt.a, v->accel, id);
+        download_scalar_ordered(h, h->pt.d, v->d, id);
+        download_scalar_ordered(h, h->pt.rho, v->rho_p, id);
         return LBDEM_OK;
     });
 }

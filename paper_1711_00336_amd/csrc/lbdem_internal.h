@@ -13,6 +13,8 @@ struct Geo {
     int n[3];
     int per[3];
     int64_t nc;
+    // invariant-divisor constants: c / nx and c / (nx*ny) as (umulhi(c,m)+c) >> s
+    uint32_t mx, sx, mxy, sxy;
 };
 
 // Model parameters in lattice units, resolved on the host.
@@ -24,6 +26,7 @@ struct Phys {
     int lub_stab, use_lub, use_am;
     int n_int, n_dem;
     double dt_int, dt_dem, c_am;
+    double kn_per_m, xi_per_m;  // k_n / m_ij and xi_n / m_ij from T_c and e_n
     double skin;                // allowed displacement within one subcycle
     int rbin;                   // DEM search radius in cells
 };
@@ -35,6 +38,7 @@ struct Cells {
     R *drho;                    // rho - 1 at step start
     R *j;                       // [3] sum_q c_q f_q at step start
     R *uprev;                   // [3] u_f of the previous step
+    R *un;                      // [3] u_f of the current post-stream state
     R *dudt;                    // [3] Du_f/Dt
     R *gradp;                   // [3] grad P
     R *epsp;                    // solid fraction 1 - eps_f of the current positions
@@ -45,19 +49,28 @@ struct Cells {
 // 1-cell bins: particles sorted by the cell of their position.
 struct Bins {
     int *cnt;                   // [nc] counts (zero between builds)
-    int *start;                 // [nc+1] exclusive prefix of cnt
-    int *list;                  // [np] particle indices, ascending within a cell
+    int *start;                 // [nc+1] exclusive prefix of cnt = slot ranges after the permutation
+    int *list;                  // [np] slot indices, ordered by (cell, id) before the permutation
     int *bsum;                  // scan block sums
 };
 
-// Particles, SoA: vectors [3][cap] (component a of particle i at a*cap+i).
+// Particles, SoA: vectors [3][cap] (component a of slot i at a*cap+i).
+// Slots are kept sorted by (cell, original index) after every rebinning, so
+// a bin is a contiguous slot range and neighbouring threads touch
+// neighbouring cells. id[i] is the insertion index of the particle in slot i.
 struct Parts {
     int64_t np, cap;
     double *x, *u, *w, *a;      // position, velocity, angular velocity, du/dt of last subcycle
     double *d, *rho;            // diameter, density
-    double *Fam, *Fd, *Fpr, *Fc;// last subcycle's fluid forces and F_const
+    int *id;
+    double *x2, *u2, *w2, *a2, *d2, *rho2;  // permutation targets
+    int *id2;
+    int *sb;                    // [3][cap] kernel stencil base cell floor(x) per axis
+    double *sw;                 // [9][cap] per-axis kernel weights, (3*axis + o+1)*cap + i
+    double *Fam, *Fd, *Fpr, *Fc;// current subcycle's fluid forces and F_const (slot order)
     double *Fdem, *Tdem;        // contact + lubrication force and torque of the substep
     double *ustart, *xstart;    // velocity / position at subcycle start
+    double *Fam_id, *Fd_id, *Fpr_id, *Fc_id;  // last subcycle's forces by insertion index
 };
 
 struct Desc {
@@ -85,7 +98,7 @@ template <typename R> void launch_moments(const Desc &D, const Cells<R> &C, hipS
 template <typename R> void launch_cellfields(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_part_am(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_am(const Desc &D, const Cells<R> &C, hipStream_t s);
-template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, int record, hipStream_t s);
 template <typename R> void launch_gather_fd(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s);
@@ -100,7 +113,8 @@ int diag_blocks(const Desc &D);
 void launch_dem_force(const Desc &D, hipStream_t s);
 void launch_integrate(const Desc &D, int last_substep, hipStream_t s);
 void launch_bin_count(const Desc &D, hipStream_t s);
-void launch_bin_build(const Desc &D, hipStream_t s);   // scan + place + per-cell sort
+void launch_bin_build(const Desc &D, hipStream_t s);   // scan + place
+void launch_sort_permute(const Desc &D, hipStream_t s); // order bins, slots <- bin order, stencils
 void launch_zero_int(int *p, int64_t n, hipStream_t s);
 void launch_set_step(long long *stepc, long long v, hipStream_t s);
 

@@ -4,9 +4,10 @@
 // Layout: cell fields are structure-of-arrays [ncomp][nc] with x fastest, so
 // a 64-lane wavefront touches 64 consecutive cells of one component. PDFs
 // are stored as deviations f_q - w_q (rho_0 = 1) in float or double.
-// Particles are SoA [3][cap] doubles. Particle -> cell transfers are gathers:
-// every cell sums the particles of its 3x3x3 neighbouring 1-cell bins, so
-// the result is deterministic and needs no floating-point atomics.
+// Particles are SoA [3][cap] doubles kept sorted by (cell, insertion index).
+// Particle -> cell transfers are gathers: every cell sums the particles of
+// its 3x3x3 neighbouring 1-cell bins (contiguous slot ranges), so the result
+// is deterministic and needs no floating-point atomics.
 #include "lbdem_internal.h"
 
 #include <cmath>
@@ -38,23 +39,39 @@ __host__ __device__ constexpr int CC(int q, int a) { return a == 0 ? CX(q) : a =
 __host__ __device__ constexpr double WQ(int q) { return q == 0 ? 1.0 / 3.0 : q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0; }
 __host__ __device__ constexpr int OPP(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
 
-__device__ __forceinline__ int wrapi(int i, int n)
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2. Remap the hardware block id so that every XCD walks one contiguous
+// range of logical blocks (a slab of cells or a run of cell-sorted
+// particles): stencil neighbours then hit the same L2. A bijection on
+// [0, nblocks) for any dispatch order, so only performance depends on it.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb)
 {
-    i %= n;
-    return i < 0 ? i + n : i;
+    const uint32_t per = nb >> 3, rem = nb & 7u, x = b & 7u, idx = b >> 3;
+    return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
 }
 
 __device__ __forceinline__ int64_t gidx(int64_t per_block = kBlock)
 {
-    return (int64_t)blockIdx.x * per_block + threadIdx.x;
+    return (int64_t)xcd_remap(blockIdx.x, gridDim.x) * per_block + threadIdx.x;
 }
 
-__device__ __forceinline__ void cell_coords(const Geo &g, int64_t c, int &i, int &j, int &k)
+// wrap a coordinate that is at most one period outside [0, n)
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t c, uint32_t m, uint32_t s)
 {
-    i = (int)(c % g.n[0]);
-    int64_t r = c / g.n[0];
-    j = (int)(r % g.n[1]);
-    k = (int)(r / g.n[1]);
+    return (__umulhi(c, m) + c) >> s;
+}
+
+__device__ __forceinline__ void cell_coords(const Geo &g, int64_t c64, int &i, int &j, int &k)
+{
+    const uint32_t c = (uint32_t)c64;
+    const uint32_t kk = fdiv(c, g.mxy, g.sxy);
+    const uint32_t rem = c - kk * (uint32_t)(g.n[0] * g.n[1]);
+    const uint32_t jj = fdiv(rem, g.mx, g.sx);
+    i = (int)(rem - jj * (uint32_t)g.n[0]);
+    j = (int)jj;
+    k = (int)kk;
 }
 
 __device__ __forceinline__ int64_t cidx(const Geo &g, int i, int j, int k)
@@ -75,55 +92,38 @@ __device__ __forceinline__ double roma(double r)
     return 0.0;
 }
 
-struct AxisSt {
-    int idx[3];
-    double w[3];
-    int m;
-};
-
-__device__ __forceinline__ void axis_stencil(double xp, int n, int per, AxisSt &s)
+// per-axis kernel weights of a particle at xp: cells b-1, b, b+1 with
+// b = floor(xp); out-of-domain cells on walled axes get weight 0 and the
+// others are divided by their sum.
+__device__ __forceinline__ void axis_weights(double xp, int n, int per, int &b, double w[3])
 {
-    const int b = (int)floor(xp);
+    b = (int)floor(xp);
+    if (per) b = b < 0 ? 0 : (b >= n ? n - 1 : b);
     double sum = 0.0;
-    s.m = 0;
 #pragma unroll
     for (int o = -1; o <= 1; ++o) {
         const int i = b + o;
-        const double w = roma((double)i + 0.5 - xp);
-        if (per) {
-            s.idx[s.m] = wrapi(i, n);
-            s.w[s.m] = w;
-            s.m++;
-        } else if (i >= 0 && i < n) {
-            s.idx[s.m] = i;
-            s.w[s.m] = w;
-            sum += w;
-            s.m++;
+        const double wo = roma((double)i + 0.5 - xp);
+        if (per || (i >= 0 && i < n)) {
+            w[o + 1] = wo;
+            sum += wo;
+        } else {
+            w[o + 1] = 0.0;
         }
     }
-    if (!per)
-        for (int t = 0; t < s.m; ++t) s.w[t] /= sum;
+    if (!per) {
+#pragma unroll
+        for (int o = 0; o < 3; ++o) w[o] /= sum;
+    }
 }
 
-// weight of cell coordinate ic in the stencil of a particle at xp (one axis)
-__device__ __forceinline__ double axis_weight(double xp, int ic, int n, int per)
+// cell coordinate of stencil offset o (clamped on walled axes, where the
+// weight of an out-of-domain offset is zero)
+__device__ __forceinline__ int stencil_coord(int b, int o, int n, int per)
 {
-    const int b = (int)floor(xp);
-    if (per) {
-        double w = 0.0;
-#pragma unroll
-        for (int o = -1; o <= 1; ++o)
-            if (wrapi(b + o, n) == ic) w += roma((double)(b + o) + 0.5 - xp);
-        return w;
-    }
-    if (ic < b - 1 || ic > b + 1) return 0.0;
-    double sum = 0.0;
-#pragma unroll
-    for (int o = -1; o <= 1; ++o) {
-        const int i = b + o;
-        if (i >= 0 && i < n) sum += roma((double)i + 0.5 - xp);
-    }
-    return roma((double)ic + 0.5 - xp) / sum;
+    int i = b + o;
+    if (per) return wrap1(i, n);
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
 // distinct wrapped coordinates c-r..c+r on one axis (walled: in range only)
@@ -134,7 +134,7 @@ __device__ __forceinline__ int axis_range(int c, int r, int n, int per, int *out
         if (2 * r + 1 >= n) {
             for (int i = 0; i < n && m < cap; ++i) out[m++] = i;
         } else {
-            for (int o = -r; o <= r; ++o) out[m++] = wrapi(c + o, n);
+            for (int o = -r; o <= r; ++o) out[m++] = wrap1(c + o, n);
         }
     } else {
         for (int o = -r; o <= r; ++o) {
@@ -180,6 +180,12 @@ __global__ __launch_bounds__(kBlock) void k_moments(Desc D, Cells<R> C)
     C.j[c] = jx;
     C.j[nc + c] = jy;
     C.j[2 * nc + c] = jz;
+    // fluid-phase velocity with the body force only (Eq. MacVel, u_f = u_bar/eps_f)
+    const double e = 1.0 - (double)C.epsp[c];
+    const double rho = 1.0 + (double)r;
+    C.un[c] = (R)(((double)jx + 0.5 * e * D.p.fb[0]) / (rho * e));
+    C.un[nc + c] = (R)(((double)jy + 0.5 * e * D.p.fb[1]) / (rho * e));
+    C.un[2 * nc + c] = (R)(((double)jz + 0.5 * e * D.p.fb[2]) / (rho * e));
 }
 
 // neighbour x + c_q with the wall ghost rule: the mirrored in-domain cell;
@@ -192,7 +198,7 @@ __device__ __forceinline__ int64_t ghost(const Geo &g, int i, int j, int k, int 
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (t[a] < 0 || t[a] >= g.n[a]) {
-            if (g.per[a]) t[a] = wrapi(t[a], g.n[a]);
+            if (g.per[a]) t[a] = wrap1(t[a], g.n[a]);
             else {
                 t[a] = t[a] < 0 ? 0 : g.n[a] - 1;
                 sign = -sign;
@@ -217,18 +223,15 @@ __global__ __launch_bounds__(kBlock) void k_cellfields(Desc D, Cells<R> C)
     if (c >= nc) return;
     int i, j, k;
     cell_coords(D.g, c, i, j, k);
-    const double fb0 = D.p.fb[0], fb1 = D.p.fb[1], fb2 = D.p.fb[2];
     double G[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     double gp[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
         double sg;
         const int64_t nb = ghost(D.g, i, j, k, q, sg);
-        const double e = 1.0 - (double)C.epsp[nb];
-        const double rho = 1.0 + (double)C.drho[nb];
-        const double u0 = ((double)C.j[nb] + 0.5 * e * fb0) / (rho * e);
-        const double u1 = ((double)C.j[nc + nb] + 0.5 * e * fb1) / (rho * e);
-        const double u2 = ((double)C.j[2 * nc + nb] + 0.5 * e * fb2) / (rho * e);
+        const double u0 = (double)C.un[nb];
+        const double u1 = (double)C.un[nc + nb];
+        const double u2 = (double)C.un[2 * nc + nb];
         const double dr = (double)C.drho[nb];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -240,12 +243,10 @@ __global__ __launch_bounds__(kBlock) void k_cellfields(Desc D, Cells<R> C)
             gp[a] += wc * dr;
         }
     }
-    const double e = 1.0 - (double)C.epsp[c];
-    const double rho = 1.0 + (double)C.drho[c];
     double un[3];
-    un[0] = ((double)C.j[c] + 0.5 * e * fb0) / (rho * e);
-    un[1] = ((double)C.j[nc + c] + 0.5 * e * fb1) / (rho * e);
-    un[2] = ((double)C.j[2 * nc + c] + 0.5 * e * fb2) / (rho * e);
+    un[0] = (double)C.un[c];
+    un[1] = (double)C.un[nc + c];
+    un[2] = (double)C.un[2 * nc + c];
     const bool have_prev = *D.stepc > 0;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
@@ -265,6 +266,21 @@ __global__ __launch_bounds__(kBlock) void k_cellfields(Desc D, Cells<R> C)
 // fluid derivative interpolated with Eq. interpolation. Also records the
 // subcycle-start velocity and position.
 // ---------------------------------------------------------------------------
+struct Stencil {
+    int b[3];
+    double w[3][3];
+};
+
+__device__ __forceinline__ void load_stencil(const Parts &P, int64_t i, Stencil &st)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        st.b[a] = P.sb[a * P.cap + i];
+#pragma unroll
+        for (int o = 0; o < 3; ++o) st.w[a][o] = P.sw[(3 * a + o) * P.cap + i];
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
 {
@@ -272,33 +288,76 @@ __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
     const Parts &P = D.pt;
     if (i >= P.np) return;
     const int64_t cap = P.cap, nc = D.g.nc;
-    const double xp[3] = {P.x[i], P.x[cap + i], P.x[2 * cap + i]};
-    AxisSt s[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) axis_stencil(xp[a], D.g.n[a], D.g.per[a], s[a]);
+    Stencil st;
+    load_stencil(P, i, st);
     double Du[3] = {0.0, 0.0, 0.0};
-    for (int cz = 0; cz < s[2].m; ++cz)
-        for (int cy = 0; cy < s[1].m; ++cy)
-            for (int cx = 0; cx < s[0].m; ++cx) {
-                const int64_t cell = cidx(D.g, s[0].idx[cx], s[1].idx[cy], s[2].idx[cz]);
-                const double w = s[0].w[cx] * s[1].w[cy] * s[2].w[cz];
+#pragma unroll 1
+    for (int oz = 0; oz < 3; ++oz) {
+        const int cz = stencil_coord(st.b[2], oz - 1, D.g.n[2], D.g.per[2]);
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+            const int cy = stencil_coord(st.b[1], oy - 1, D.g.n[1], D.g.per[1]);
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) {
+                const int cx = stencil_coord(st.b[0], ox - 1, D.g.n[0], D.g.per[0]);
+                const int64_t cell = cidx(D.g, cx, cy, cz);
+                const double w = st.w[0][ox] * st.w[1][oy] * st.w[2][oz];
 #pragma unroll
                 for (int b = 0; b < 3; ++b) Du[b] += w * (double)C.dudt[b * nc + cell];
             }
+        }
+    }
     const double V = sphere_volume(P.d[i]);
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         const double F = D.p.use_am ? D.p.c_am * D.p.rho_f * V * (Du[b] - P.a[b * cap + i]) : 0.0;
         P.Fam[b * cap + i] = F;
         P.ustart[b * cap + i] = P.u[b * cap + i];
-        P.xstart[b * cap + i] = xp[b];
+        P.xstart[b * cap + i] = P.x[b * cap + i];
     }
 }
 
 // ---------------------------------------------------------------------------
 // Gather of a particle quantity to one cell (Eq. distribution_filter with
-// D = I): s = sum_p D(x, x_p) v_p over particles in the 27 neighbouring bins.
+// D = I): s = sum_p D(x, x_p) v_p over the particles of the 3x3x3
+// neighbouring bins. Slots are sorted by cell, so each x-row of three bins is
+// one contiguous slot range.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double stencil_w(const Parts &P, int64_t p, int axis, int ic, int n, int per)
+{
+    const int b = P.sb[axis * P.cap + p];
+    const double *sw = P.sw + (int64_t)(3 * axis) * P.cap + p;
+    int o = ic - b;
+    if (per) {
+        if (n < 3) {  // several stencil offsets land on the same cell
+            double w = 0.0;
+#pragma unroll
+            for (int t = -1; t <= 1; ++t)
+                if (wrap1(b + t, n) == ic) w += sw[(t + 1) * P.cap];
+            return w;
+        }
+        o = o > 1 ? o - n : (o < -1 ? o + n : o);
+    }
+    return (o >= -1 && o <= 1) ? sw[(o + 1) * P.cap] : 0.0;
+}
+
+template <int NV, typename F>
+__device__ __forceinline__ void gather_range(const Desc &D, int i, int j, int k, int p0, int p1, const F &val,
+                                             double *s)
+{
+    for (int p = p0; p < p1; ++p) {
+        const double wx = stencil_w(D.pt, p, 0, i, D.g.n[0], D.g.per[0]);
+        const double wy = stencil_w(D.pt, p, 1, j, D.g.n[1], D.g.per[1]);
+        const double wz = stencil_w(D.pt, p, 2, k, D.g.n[2], D.g.per[2]);
+        const double w = wx * wy * wz;
+        if (w == 0.0) continue;
+        double v[NV];
+        val(p, v);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) s[q] += w * v[q];
+    }
+}
+
 template <int NV, typename F>
 __device__ __forceinline__ void gather_cell(const Desc &D, int i, int j, int k, const F &val, double *s)
 {
@@ -306,48 +365,205 @@ __device__ __forceinline__ void gather_cell(const Desc &D, int i, int j, int k, 
     const int mx = axis_range(i, 1, D.g.n[0], D.g.per[0], cx, 3);
     const int my = axis_range(j, 1, D.g.n[1], D.g.per[1], cy, 3);
     const int mz = axis_range(k, 1, D.g.n[2], D.g.per[2], cz, 3);
-    const int64_t cap = D.pt.cap;
+    // one contiguous x-run of bins when the row does not wrap
+    const bool run = mx == 3 && cx[0] + 2 == cx[2];
 #pragma unroll
     for (int t = 0; t < NV; ++t) s[t] = 0.0;
     for (int a = 0; a < mz; ++a)
-        for (int b = 0; b < my; ++b)
-            for (int c = 0; c < mx; ++c) {
-                const int64_t bin = cidx(D.g, cx[c], cy[b], cz[a]);
-                const int p0 = D.b.start[bin], p1 = D.b.start[bin + 1];
-                for (int t = p0; t < p1; ++t) {
-                    const int p = D.b.list[t];
-                    const double wx = axis_weight(D.pt.x[p], i, D.g.n[0], D.g.per[0]);
-                    const double wy = axis_weight(D.pt.x[cap + p], j, D.g.n[1], D.g.per[1]);
-                    const double wz = axis_weight(D.pt.x[2 * cap + p], k, D.g.n[2], D.g.per[2]);
-                    const double w = wx * wy * wz;
-                    if (w == 0.0) continue;
-                    double v[NV];
-                    val(p, v);
-#pragma unroll
-                    for (int q = 0; q < NV; ++q) s[q] += w * v[q];
+        for (int b = 0; b < my; ++b) {
+            if (run) {
+                const int64_t b0 = cidx(D.g, cx[0], cy[b], cz[a]);
+                gather_range<NV>(D, i, j, k, D.b.start[b0], D.b.start[b0 + 3], val, s);
+            } else {
+                for (int c = 0; c < mx; ++c) {
+                    const int64_t bin = cidx(D.g, cx[c], cy[b], cz[a]);
+                    gather_range<NV>(D, i, j, k, D.b.start[bin], D.b.start[bin + 1], val, s);
                 }
             }
+        }
 }
 
-// fam = -sum_p D F_am (the added-mass part of f_p->f, Eq. forces_pf)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_gather_am(Desc D, Cells<R> C)
+// ---------------------------------------------------------------------------
+// LDS-tiled gather. A workgroup owns a TX x TY x TZ tile of cells. It counts
+// the particles of the tile's halo bins (the tile widened by one cell, wrapped
+// on periodic axes), stages their stencils and values into LDS with coalesced
+// loads (bins are contiguous slot ranges), and then every cell sums the
+// particles of its own 3x3x3 bins from LDS. Tiles whose halo holds more than
+// KMAX particles fall back to the per-cell global gather.
+//   MODE_AM : fam  = -sum_p D F_am                    (Eq. forces_pf, added mass)
+//   MODE_FD : facc += (eps_f f_b + fam - sum_p D F_d) / n_int   (mean f_ext)
+//   MODE_EPS: epsp = sum_p D V_p                      (Eq. fluid_volume_fraction)
+// ---------------------------------------------------------------------------
+enum { MODE_AM = 0, MODE_FD = 1, MODE_EPS = 2 };
+
+template <int MODE>
+__device__ __forceinline__ void gather_value(const Parts &P, int p, double *v)
+{
+    if (MODE == MODE_EPS) {
+        v[0] = sphere_volume(P.d[p]);
+    } else {
+        const double *F = MODE == MODE_AM ? P.Fam : P.Fd;
+        v[0] = F[p];
+        v[1] = F[P.cap + p];
+        v[2] = F[2 * P.cap + p];
+    }
+}
+
+template <typename R, int MODE>
+__device__ __forceinline__ void gather_store(const Desc &D, const Cells<R> &C, int64_t c, const double *s)
+{
+    const int64_t nc = D.g.nc;
+    if (MODE == MODE_AM) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) C.fam[b * nc + c] = (R)(-s[b]);
+    } else if (MODE == MODE_FD) {
+        const double e = 1.0 - (double)C.epsp[c];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double fext = e * D.p.fb[b] + (double)C.fam[b * nc + c] - s[b];
+            C.facc[b * nc + c] = (R)((double)C.facc[b * nc + c] + fext * D.p.dt_int);
+        }
+    } else {
+        const double e = 1.0 - s[0];
+        if (!(e > 0.0) || !isfinite(e)) atomicOr(D.flags, FLAG_EPS);
+        C.epsp[c] = (R)s[0];
+    }
+}
+
+template <typename R, int MODE, int TX, int TY, int TZ, int KMAX>
+__global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
+{
+    constexpr int NT = TX * TY * TZ, HX = TX + 2, HY = TY + 2, HZ = TZ + 2, NHB = HX * HY * HZ;
+    constexpr int NV = MODE == MODE_EPS ? 1 : 3;
+    constexpr int PER = (NHB + NT - 1) / NT;
+    __shared__ int hoff[NHB + 1];
+    __shared__ int hsrc[NHB];
+    __shared__ int sscan[NT];
+    __shared__ double sw_l[9][KMAX];
+    __shared__ double sv_l[NV][KMAX];
+
+    const int tid = threadIdx.x;
+    const int n0 = D.g.n[0], n1 = D.g.n[1], n2 = D.g.n[2];
+    const uint32_t lin = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                   gridDim.x * gridDim.y * gridDim.z);
+    const int bx = (int)(lin % gridDim.x), by = (int)((lin / gridDim.x) % gridDim.y),
+              bz = (int)(lin / (gridDim.x * gridDim.y));
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    // halo bins beyond the last cell of a partial tile (+1) are not needed
+    const int lx = min(x0 + TX, n0) - x0 + 1, ly = min(y0 + TY, n1) - y0 + 1, lz = min(z0 + TZ, n2) - z0 + 1;
+
+    int cl[PER];
+    int sum = 0;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int hb = tid * PER + t;
+        int cnt = 0, src = 0;
+        if (hb < NHB) {
+            const int hx = hb % HX, hy = (hb / HX) % HY, hz = hb / (HX * HY);
+            int g[3] = {x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz};
+            bool ok = hx <= lx && hy <= ly && hz <= lz;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (g[a] < 0 || g[a] >= D.g.n[a]) {
+                    if (D.g.per[a]) g[a] = wrap1(g[a], D.g.n[a]);
+                    else ok = false;
+                }
+            }
+            if (ok) {
+                const int64_t bin = cidx(D.g, g[0], g[1], g[2]);
+                src = D.b.start[bin];
+                cnt = D.b.start[bin + 1] - src;
+            }
+            hsrc[hb] = src;
+        }
+        cl[t] = cnt;
+        sum += cnt;
+    }
+    sscan[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < NT; off <<= 1) {
+        const int add = tid >= off ? sscan[tid - off] : 0;
+        __syncthreads();
+        sscan[tid] += add;
+        __syncthreads();
+    }
+    int run = sscan[tid] - sum;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+        const int hb = tid * PER + t;
+        if (hb < NHB) hoff[hb] = run;
+        run += cl[t];
+    }
+    if (tid == NT - 1) hoff[NHB] = sscan[NT - 1];
+    __syncthreads();
+    const int K = hoff[NHB];
+
+    const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
+    const int i = x0 + tx, j = y0 + ty, k = z0 + tz;
+    const bool inside = i < n0 && j < n1 && k < n2;
+    const int64_t c = inside ? cidx(D.g, i, j, k) : 0;
+    double s[NV];
+
+    if (K > KMAX) {  // crowded tile: per-cell gather from global memory
+        if (!inside) return;
+        gather_cell<NV>(D, i, j, k, [&](int p, double *v) { gather_value<MODE>(D.pt, p, v); }, s);
+        gather_store<R, MODE>(D, C, c, s);
+        return;
+    }
+
+    const Parts &P = D.pt;
+    for (int kk = tid; kk < K; kk += NT) {
+        int lo = 0, hi = NHB - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (hoff[mid] <= kk) lo = mid;
+            else hi = mid - 1;
+        }
+        const int p = hsrc[lo] + (kk - hoff[lo]);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) sw_l[t][kk] = P.sw[t * P.cap + p];
+        double v[NV];
+        gather_value<MODE>(P, p, v);
+#pragma unroll
+        for (int t = 0; t < NV; ++t) sv_l[t][kk] = v[t];
+    }
+    __syncthreads();
+    if (!inside) return;
+
+#pragma unroll
+    for (int t = 0; t < NV; ++t) s[t] = 0.0;
+    // The bin of a staged particle fixes its stencil offset relative to this
+    // cell: a particle in bin (i-1+dx, j-1+dy, k-1+dz) sees the cell at offset
+    // (1-dx, 1-dy, 1-dz), i.e. weight slots 2-dx, 2-dy, 2-dz of its axes.
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+            const int hb0 = ((tz + dz) * HY + (ty + dy)) * HX + tx;
+            const int k0 = hoff[hb0], k1 = hoff[hb0 + 1], k2 = hoff[hb0 + 2], k3 = hoff[hb0 + 3];
+            for (int kk = k0; kk < k3; ++kk) {
+                const int sx = kk < k1 ? 2 : (kk < k2 ? 1 : 0);
+                const double w = sw_l[sx][kk] * sw_l[3 + 2 - dy][kk] * sw_l[6 + 2 - dz][kk];
+#pragma unroll
+                for (int t = 0; t < NV; ++t) s[t] += w * sv_l[t][kk];
+            }
+        }
+    gather_store<R, MODE>(D, C, c, s);
+}
+
+// per-cell global gather (thin periodic axes, where a cell's neighbour bins coincide)
+template <typename R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_gather_cells(Desc D, Cells<R> C)
 {
     const int64_t nc = D.g.nc;
     const int64_t c = gidx();
     if (c >= nc) return;
     int i, j, k;
     cell_coords(D.g, c, i, j, k);
-    const int64_t cap = D.pt.cap;
-    const double *Fam = D.pt.Fam;
-    double s[3];
-    gather_cell<3>(D, i, j, k, [&](int p, double *v) {
-        v[0] = Fam[p];
-        v[1] = Fam[cap + p];
-        v[2] = Fam[2 * cap + p];
-    }, s);
-#pragma unroll
-    for (int b = 0; b < 3; ++b) C.fam[b * nc + c] = (R)(-s[b]);
+    constexpr int NV = MODE == MODE_EPS ? 1 : 3;
+    double s[NV];
+    gather_cell<NV>(D, i, j, k, [&](int p, double *v) { gather_value<MODE>(D.pt, p, v); }, s);
+    gather_store<R, MODE>(D, C, c, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -366,34 +582,41 @@ __device__ __forceinline__ double drag_factor(double Re, double ep)
 }
 
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_part_drag(Desc D, Cells<R> C)
+__global__ __launch_bounds__(kBlock) void k_part_drag(Desc D, Cells<R> C, int record)
 {
     const int64_t i = gidx();
     const Parts &P = D.pt;
     if (i >= P.np) return;
     const int64_t cap = P.cap, nc = D.g.nc;
-    const double xp[3] = {P.x[i], P.x[cap + i], P.x[2 * cap + i]};
-    AxisSt s[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) axis_stencil(xp[a], D.g.n[a], D.g.per[a], s[a]);
+    Stencil st;
+    load_stencil(P, i, st);
     double uf[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, ep = 0.0;
-    for (int cz = 0; cz < s[2].m; ++cz)
-        for (int cy = 0; cy < s[1].m; ++cy)
-            for (int cx = 0; cx < s[0].m; ++cx) {
-                const int64_t cell = cidx(D.g, s[0].idx[cx], s[1].idx[cy], s[2].idx[cz]);
-                const double w = s[0].w[cx] * s[1].w[cy] * s[2].w[cz];
+#pragma unroll 1
+    for (int oz = 0; oz < 3; ++oz) {
+        const int cz = stencil_coord(st.b[2], oz - 1, D.g.n[2], D.g.per[2]);
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+            const int cy = stencil_coord(st.b[1], oy - 1, D.g.n[1], D.g.per[1]);
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) {
+                const int cx = stencil_coord(st.b[0], ox - 1, D.g.n[0], D.g.per[0]);
+                const int64_t cell = cidx(D.g, cx, cy, cz);
+                const double w = st.w[0][ox] * st.w[1][oy] * st.w[2][oz];
                 const double epc = (double)C.epsp[cell];
                 const double e = 1.0 - epc;
                 const double rho = 1.0 + (double)C.drho[cell];
+                const double inv = 1.0 / (rho * e);
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
                     const double fext = e * D.p.fb[b] + (double)C.fam[b * nc + cell];
-                    const double ub = ((double)C.j[b * nc + cell] + 0.5 * fext) / (rho * e);
+                    const double ub = ((double)C.j[b * nc + cell] + 0.5 * fext) * inv;
                     uf[b] += w * ub;
                     gp[b] += w * (double)C.gradp[b * nc + cell];
                 }
                 ep += w * epc;
             }
+        }
+    }
     const double d = P.d[i];
     const double V = sphere_volume(d);
     double wv[3];
@@ -403,57 +626,23 @@ __global__ __launch_bounds__(kBlock) void k_part_drag(Desc D, Cells<R> C)
     const double Re = (1.0 - ep) * D.p.rho_f * d * wn / D.p.mu;
     const double fac = 3.0 * M_PI * d * D.p.mu * drag_factor(Re, ep);
     const double rp = P.rho[i];
+    const int pid = P.id[i];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         const double Fpr = -V * gp[b];
         const double Fd = fac * wv[b];
         const double fgb = (rp - D.p.rho_f) * V * D.p.g[b];
-        P.Fpr[b * cap + i] = Fpr;
+        const double Fam = P.Fam[b * cap + i];
+        const double Fc = Fd + Fpr + Fam + fgb;
         P.Fd[b * cap + i] = Fd;
-        P.Fc[b * cap + i] = Fd + Fpr + P.Fam[b * cap + i] + fgb;
+        P.Fc[b * cap + i] = Fc;
+        if (record) {
+            P.Fam_id[b * cap + pid] = Fam;
+            P.Fd_id[b * cap + pid] = Fd;
+            P.Fpr_id[b * cap + pid] = Fpr;
+            P.Fc_id[b * cap + pid] = Fc;
+        }
     }
-}
-
-// f_acc += (eps_f f_b + f_am - sum_p D F_d) / n_int   (Alg. 1, mean f_ext)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_gather_fd(Desc D, Cells<R> C)
-{
-    const int64_t nc = D.g.nc;
-    const int64_t c = gidx();
-    if (c >= nc) return;
-    int i, j, k;
-    cell_coords(D.g, c, i, j, k);
-    const int64_t cap = D.pt.cap;
-    const double *Fd = D.pt.Fd;
-    double s[3];
-    gather_cell<3>(D, i, j, k, [&](int p, double *v) {
-        v[0] = Fd[p];
-        v[1] = Fd[cap + p];
-        v[2] = Fd[2 * cap + p];
-    }, s);
-    const double e = 1.0 - (double)C.epsp[c];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        const double fext = e * D.p.fb[b] + (double)C.fam[b * nc + c] - s[b];
-        C.facc[b * nc + c] = (R)((double)C.facc[b * nc + c] + fext * D.p.dt_int);
-    }
-}
-
-// a9: solid fraction of the current positions (Eq. fluid_volume_fraction)
-template <typename R>
-__global__ __launch_bounds__(kBlock) void k_gather_eps(Desc D, Cells<R> C)
-{
-    const int64_t nc = D.g.nc;
-    const int64_t c = gidx();
-    if (c >= nc) return;
-    int i, j, k;
-    cell_coords(D.g, c, i, j, k);
-    const double *d = D.pt.d;
-    double s[1];
-    gather_cell<1>(D, i, j, k, [&](int p, double *v) { v[0] = sphere_volume(d[p]); }, s);
-    const double e = 1.0 - s[0];
-    if (!(e > 0.0) || !isfinite(e)) atomicOr(D.flags, FLAG_EPS);
-    C.epsp[c] = (R)s[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -480,9 +669,8 @@ __device__ __forceinline__ double dot3(const double a[3], const double b[3])
 __device__ __forceinline__ void contact(const Phys &p, double delta, const double n[3], const double ur[3],
                                         double mij, double ri, double F[3], double T[3])
 {
-    const double L = log(p.e_n);
-    const double kn = mij * (M_PI * M_PI + L * L) / (p.T_c * p.T_c);
-    const double xi = -2.0 * L * mij / p.T_c;
+    const double kn = mij * p.kn_per_m;
+    const double xi = mij * p.xi_per_m;
     const double urn_s = dot3(ur, n);
     double urn[3], urt[3], Fn[3];
 #pragma unroll
@@ -590,12 +778,30 @@ __device__ __forceinline__ void load_pv(const Parts &P, int64_t i, PV &v)
     }
 }
 
+// Two phases per particle: the candidate scan only collects partners within
+// interaction reach into an LDS list; the force evaluation then runs over
+// that list, so lanes do not idle through each other's expensive pairs. If a
+// particle has more than kPBuf partners the scan is repeated for the rest.
+constexpr int kPBuf = 24;
+
+__device__ __forceinline__ void min_image(const Geo &g, double dx[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (g.per[a]) {
+            const double L = (double)g.n[a];
+            dx[a] = dx[a] > 0.5 * L ? dx[a] - L : (dx[a] < -0.5 * L ? dx[a] + L : dx[a]);
+        }
+}
+
 __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
 {
+    __shared__ int nbr[kPBuf][kBlock];
     const int64_t i = gidx();
     const Parts &P = D.pt;
     if (i >= P.np) return;
     const int64_t cap = P.cap;
+    const int tid = threadIdx.x;
     PV pi;
     load_pv(P, i, pi);
     double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
@@ -606,28 +812,45 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
     constexpr int kMaxR = 8;
     int cx[2 * kMaxR + 1], cy[2 * kMaxR + 1], cz[2 * kMaxR + 1];
     const int R = D.p.rbin;
+    const double reach_gap = D.p.use_lub ? fmax(D.p.h_c, 0.0) : 0.0;
     const int mx = axis_range(b[0], R, D.g.n[0], D.g.per[0], cx, 2 * kMaxR + 1);
     const int my = axis_range(b[1], R, D.g.n[1], D.g.per[1], cy, 2 * kMaxR + 1);
     const int mz = axis_range(b[2], R, D.g.n[2], D.g.per[2], cz, 2 * kMaxR + 1);
-    for (int c2 = 0; c2 < mz; ++c2)
-        for (int c1 = 0; c1 < my; ++c1)
-            for (int c0 = 0; c0 < mx; ++c0) {
-                const int64_t bin = cidx(D.g, cx[c0], cy[c1], cz[c2]);
-                const int p0 = D.b.start[bin], p1 = D.b.start[bin + 1];
-                for (int t = p0; t < p1; ++t) {
-                    const int jdx = D.b.list[t];
-                    if (jdx == i) continue;
-                    PV pj;
-                    load_pv(P, jdx, pj);
-                    double dx[3];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        dx[a] = pj.x[a] - pi.x[a];
-                        if (D.g.per[a]) dx[a] -= D.g.n[a] * rint(dx[a] / D.g.n[a]);
+    // slots are sorted by cell: a non-wrapping x-row of bins is one slot range
+    const bool run = mx >= 1 && cx[mx - 1] - cx[0] == mx - 1;
+    const int nrun = run ? 1 : mx;
+    int skip = 0;
+    bool more = true;
+    while (more) {
+        more = false;
+        int m = 0, seen = 0;
+        for (int c2 = 0; c2 < mz; ++c2)
+            for (int c1 = 0; c1 < my; ++c1)
+                for (int c0 = 0; c0 < nrun; ++c0) {
+                    const int64_t bin = cidx(D.g, cx[c0], cy[c1], cz[c2]);
+                    const int p0 = D.b.start[bin];
+                    const int p1 = D.b.start[bin + (run ? mx : 1)];
+                    for (int jdx = p0; jdx < p1; ++jdx) {
+                        if (jdx == i) continue;
+                        double dx[3] = {P.x[jdx] - pi.x[0], P.x[cap + jdx] - pi.x[1], P.x[2 * cap + jdx] - pi.x[2]};
+                        min_image(D.g, dx);
+                        const double reach = pi.r + 0.5 * P.d[jdx] + reach_gap;
+                        if (dot3(dx, dx) >= reach * reach) continue;
+                        if (seen++ < skip) continue;
+                        if (m < kPBuf) nbr[m++][tid] = jdx;
+                        else more = true;
                     }
-                    pair_interaction(D.p, pi, pj, dx, F, T);
                 }
-            }
+        for (int t = 0; t < m; ++t) {
+            const int jdx = nbr[t][tid];
+            PV pj;
+            load_pv(P, jdx, pj);
+            double dx[3] = {pj.x[0] - pi.x[0], pj.x[1] - pi.x[1], pj.x[2] - pi.x[2]};
+            min_image(D.g, dx);
+            pair_interaction(D.p, pi, pj, dx, F, T);
+        }
+        skip += m;
+    }
     wall_interaction(D.p, D.g, pi, F, T);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -768,23 +991,55 @@ __global__ __launch_bounds__(kBlock) void k_place(Desc D)
     D.b.list[pos] = (int)i;
 }
 
-// order each bin by particle index (deterministic sums) and reset the counts
+// order each bin by insertion index (so that every sum over a bin runs in a
+// history-independent order) and reset the counts
 __global__ __launch_bounds__(kBlock) void k_cellsort(Desc D)
 {
     const int64_t nc = D.g.nc;
     const int64_t c = gidx();
     if (c >= nc) return;
+    D.b.cnt[c] = 0;
     const int p0 = D.b.start[c], p1 = D.b.start[c + 1];
+    const int *id = D.pt.id;
+    int *L = D.b.list;
     for (int a = p0 + 1; a < p1; ++a) {
-        const int v = D.b.list[a];
+        const int v = L[a];
+        const int key = id[v];
         int b = a - 1;
-        while (b >= p0 && D.b.list[b] > v) {
-            D.b.list[b + 1] = D.b.list[b];
+        while (b >= p0 && id[L[b]] > key) {
+            L[b + 1] = L[b];
             --b;
         }
-        D.b.list[b + 1] = v;
+        L[b + 1] = v;
     }
-    D.b.cnt[c] = 0;
+}
+
+// gather the particle state into bin order (slot s <- list[s]) and evaluate
+// the kernel stencils of the new positions
+__global__ __launch_bounds__(kBlock) void k_permute(Desc D)
+{
+    const int64_t s = gidx();
+    const Parts &P = D.pt;
+    if (s >= P.np) return;
+    const int64_t cap = P.cap;
+    const int src = D.b.list[s];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double xa = P.x[a * cap + src];
+        P.x2[a * cap + s] = xa;
+        P.u2[a * cap + s] = P.u[a * cap + src];
+        P.w2[a * cap + s] = P.w[a * cap + src];
+        P.a2[a * cap + s] = P.a[a * cap + src];
+        int b;
+        double w[3];
+        axis_weights(xa, D.g.n[a], D.g.per[a], b, w);
+        P.sb[a * cap + s] = b;
+#pragma unroll
+        for (int o = 0; o < 3; ++o) P.sw[(3 * a + o) * cap + s] = w[o];
+    }
+    P.d2[s] = P.d[src];
+    P.rho2[s] = P.rho[src];
+    P.id2[s] = P.id[src];
 }
 
 // ---------------------------------------------------------------------------
@@ -966,21 +1221,40 @@ template <typename R> void launch_part_am(const Desc &D, const Cells<R> &C, hipS
 {
     if (D.pt.np > 0) hipLaunchKernelGGL(k_part_am<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
 }
+// tile shapes: a dilute variant (16x4x4 cells, up to 384 staged particles)
+// and a dense one (8x4x4, up to 512); periodic axes thinner than 3 cells use
+// the per-cell gather
+template <typename R, int MODE> void launch_gather(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    const bool thin = (D.g.per[0] && D.g.n[0] < 3) || (D.g.per[1] && D.g.n[1] < 3) || (D.g.per[2] && D.g.n[2] < 3);
+    if (thin) {
+        hipLaunchKernelGGL((k_gather_cells<R, MODE>), dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+        return;
+    }
+    const double density = D.g.nc > 0 ? (double)D.pt.np / (double)D.g.nc : 0.0;
+    if (density < 0.3) {
+        dim3 grid((D.g.n[0] + 15) / 16, (D.g.n[1] + 3) / 4, (D.g.n[2] + 3) / 4);
+        hipLaunchKernelGGL((k_gather_tile<R, MODE, 16, 4, 4, 384>), grid, dim3(256), 0, s, D, C);
+    } else {
+        dim3 grid((D.g.n[0] + 7) / 8, (D.g.n[1] + 3) / 4, (D.g.n[2] + 3) / 4);
+        hipLaunchKernelGGL((k_gather_tile<R, MODE, 8, 4, 4, 512>), grid, dim3(128), 0, s, D, C);
+    }
+}
 template <typename R> void launch_gather_am(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_am<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+    launch_gather<R, MODE_AM>(D, C, s);
 }
-template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, hipStream_t s)
+template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, int record, hipStream_t s)
 {
-    if (D.pt.np > 0) hipLaunchKernelGGL(k_part_drag<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
+    if (D.pt.np > 0) hipLaunchKernelGGL(k_part_drag<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C, record);
 }
 template <typename R> void launch_gather_fd(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_fd<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+    launch_gather<R, MODE_FD>(D, C, s);
 }
 template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gather_eps<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+    launch_gather<R, MODE_EPS>(D, C, s);
 }
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
@@ -1034,7 +1308,11 @@ void launch_bin_build(const Desc &D, hipStream_t s)
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, D.b.bsum, (int)nb, D.b.start + D.g.nc);
     hipLaunchKernelGGL(k_scan_add, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D);
     if (D.pt.np > 0) hipLaunchKernelGGL(k_place, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+}
+void launch_sort_permute(const Desc &D, hipStream_t s)
+{
     hipLaunchKernelGGL(k_cellsort, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D);
+    if (D.pt.np > 0) hipLaunchKernelGGL(k_permute, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
 }
 void launch_zero_int(int *p, int64_t n, hipStream_t s) { launch_zero<int>(p, n, s); }
 void launch_set_step(long long *stepc, long long v, hipStream_t s)
@@ -1047,7 +1325,7 @@ void launch_set_step(long long *stepc, long long v, hipStream_t s)
     template void launch_cellfields<R>(const Desc &, const Cells<R> &, hipStream_t);                       \
     template void launch_part_am<R>(const Desc &, const Cells<R> &, hipStream_t);                          \
     template void launch_gather_am<R>(const Desc &, const Cells<R> &, hipStream_t);                        \
-    template void launch_part_drag<R>(const Desc &, const Cells<R> &, hipStream_t);                        \
+    template void launch_part_drag<R>(const Desc &, const Cells<R> &, int, hipStream_t);                        \
     template void launch_gather_fd<R>(const Desc &, const Cells<R> &, hipStream_t);                        \
     template void launch_gather_eps<R>(const Desc &, const Cells<R> &, hipStream_t);                       \
     template void launch_stream_collide<R>(const Desc &, const Cells<R> &, hipStream_t);                   \

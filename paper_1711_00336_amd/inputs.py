@@ -85,6 +85,7 @@ class Params:
     use_lub: int = 1
     use_am: int = 1
     precision: str = "fp64"                 # "fp64" | "fp32dev"
+    flags: int = 0                          # library flags (1: no graph replay)
 
     def copy(self, **kw) -> "Params":
         d = asdict(self)

@@ -20,6 +20,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 FIELD_DRHO, FIELD_J, FIELD_EPS_F, FIELD_F_ACC, FIELD_DUDT, FIELD_GRADP, FIELD_UPREV, FIELD_PDF = range(8)
 FIELD_NCOMP = {FIELD_DRHO: 1, FIELD_J: 3, FIELD_EPS_F: 1, FIELD_F_ACC: 3, FIELD_DUDT: 3,
                FIELD_GRADP: 3, FIELD_UPREV: 3, FIELD_PDF: 19}
+FLAG_NO_GRAPH = 1
 KCLASS = {"stream_collide": 0, "moments": 1, "cellfields": 2, "particles": 3, "gathers": 4,
           "dem": 5, "bins": 6}
 
@@ -122,6 +123,7 @@ def params_from(prm) -> lbdem_params:
     P.n_int, P.n_dem = int(prm.n_int), int(prm.n_dem)
     P.c_am = prm.c_am
     P.precision = FP32_DEV if prm.precision == "fp32dev" else FP64
+    P.flags = int(getattr(prm, "flags", 0))
     return P
 
 
