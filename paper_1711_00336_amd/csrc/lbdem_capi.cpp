@@ -59,7 +59,7 @@ struct lbdem_domain {
     void *df[2] = {nullptr, nullptr};
     int cur = 0;
     void *drho = nullptr, *j = nullptr, *uprev = nullptr, *un = nullptr, *dudt = nullptr, *gradp = nullptr;
-    void *epsp = nullptr, *fam = nullptr, *facc = nullptr;
+    void *epsp = nullptr, *fam = nullptr, *uf = nullptr, *facc = nullptr;
     // bins
     int *cnt = nullptr, *start = nullptr, *list = nullptr, *bsum = nullptr;
     int64_t list_cap = 0;
@@ -153,6 +153,7 @@ struct lbdem_domain {
         C.gradp = (R *)gradp;
         C.epsp = (R *)epsp;
         C.fam = (R *)fam;
+        C.uf = (R *)uf;
         C.facc = (R *)facc;
         return C;
     }
@@ -269,13 +270,15 @@ void resolve_phys(lbdem_domain_t h)
     P.xi_per_m = -2.0 * L / P.T_c;
     P.c_am = p.c_am;
     P.skin = 0.1;
+    P.vskin = 0.4;
     P.rbin = 1;
 }
 
 void update_search(lbdem_domain_t h)
 {
     Phys &P = h->phys;
-    const double reach = h->dmax + (P.use_lub ? std::max(P.h_c, 0.0) : 0.0) + 2.0 * P.skin;
+    // list build runs on current bins: reach d_max + h_c + Verlet skin
+    const double reach = h->dmax + (P.use_lub ? std::max(P.h_c, 0.0) : 0.0) + P.vskin;
     P.rbin = std::max(1, (int)std::ceil(reach));
     if (P.rbin > 8) throw std::runtime_error("interaction reach d_max + h_c exceeds the 8-cell search limit");
 }
@@ -316,6 +319,7 @@ void sort_particles(lbdem_domain_t h)
 template <typename R>
 void rebuild_particle_fields(lbdem_domain_t h)
 {
+    launch_set_int(h->pt.need, 1, h->stream);
     launch_zero_int(h->cnt, h->geo.nc, h->stream);
     launch_bin_count(h->desc(), h->stream);
     sort_particles(h);
@@ -360,6 +364,14 @@ void alloc_particles(lbdem_domain_t h, int64_t cap)
         *v = (int *)h->dalloc(sizeof(int) * c);
         hip_check(hipMemsetAsync(*v, 0, sizeof(int) * c, h->stream), "hipMemsetAsync");
     }
+    for (int **v : {&P.nlist, &P.nnb, &P.slot_of}) h->dfree(*v);
+    h->dfree(P.xbuild);
+    P.nlist = (int *)h->dalloc(sizeof(int) * (size_t)kNbr * c);
+    P.nnb = (int *)h->dalloc(sizeof(int) * c);
+    P.slot_of = (int *)h->dalloc(sizeof(int) * c);
+    P.xbuild = (double *)h->dalloc(sizeof(double) * 3 * c);
+    hip_check(hipMemsetAsync(P.nnb, 0, sizeof(int) * c, h->stream), "hipMemsetAsync");
+    hip_check(hipMemsetAsync(P.xbuild, 0, sizeof(double) * 3 * c, h->stream), "hipMemsetAsync");
     P.sb = (int *)h->dalloc(sizeof(int) * 3 * c);
     P.sw = (double *)h->dalloc(sizeof(double) * 9 * c);
     hip_check(hipMemsetAsync(P.sb, 0, sizeof(int) * 3 * c, h->stream), "hipMemsetAsync");
@@ -483,25 +495,35 @@ void check_particles(lbdem_domain_t h, int64_t n, const double *x, const double 
     }
 }
 
+// One coupled step, Alg. 1. The volume-fraction update that closes
+// subcycle k and the added-mass spreading that opens subcycle k+1 use the
+// same positions and bins, so they share one gather pass.
 template <typename R>
 void enqueue_step(lbdem_domain_t h)
 {
     hipStream_t s = h->stream;
     const Cells<R> C = h->cells<R>();
+    const int nint = h->phys.n_int;
     launch_cls(h, 1, [&] { launch_moments<R>(h->desc(), C, s); });
     launch_cls(h, 2, [&] { launch_cellfields<R>(h->desc(), C, s); });
-    for (int k = 0; k < h->phys.n_int; ++k) {
-        const int last_sub = k == h->phys.n_int - 1;
-        launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
-        launch_cls(h, 4, [&] { launch_gather_am<R>(h->desc(), C, s); });
+    launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
+    launch_cls(h, 4, [&] { launch_gather_am<R>(h->desc(), C, s); });
+    for (int k = 0; k < nint; ++k) {
+        const int last_sub = k == nint - 1;
         launch_cls(h, 3, [&] { launch_part_drag<R>(h->desc(), C, last_sub, s); });
         launch_cls(h, 4, [&] { launch_gather_fd<R>(h->desc(), C, s); });
+        launch_cls(h, 5, [&] { launch_nlist(h->desc(), s); });
         for (int sub = 0; sub < h->phys.n_dem; ++sub) {
             launch_cls(h, 5, [&] { launch_dem_force(h->desc(), s); });
             launch_cls(h, 5, [&] { launch_integrate(h->desc(), sub == h->phys.n_dem - 1, s); });
         }
         launch_cls(h, 6, [&] { sort_particles(h); });
-        launch_cls(h, 4, [&] { launch_gather_eps<R>(h->desc(), C, s); });
+        if (!last_sub) {
+            launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
+            launch_cls(h, 4, [&] { launch_gather_eps_am<R>(h->desc(), C, s); });
+        } else {
+            launch_cls(h, 4, [&] { launch_gather_eps<R>(h->desc(), C, s); });
+        }
     }
     launch_cls(h, 0, [&] { launch_stream_collide<R>(h->desc(), C, s); });
     hip_check(hipGetLastError(), "kernel launch");
@@ -673,17 +695,20 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
         h->gradp = h->dalloc(rs * 3 * nc);
         h->epsp = h->dalloc(rs * nc);
         h->fam = h->dalloc(rs * 3 * nc);
+        h->uf = h->dalloc(rs * 3 * nc);
         h->facc = h->dalloc(rs * 3 * nc);
         h->cnt = (int *)h->dalloc(sizeof(int) * nc);
         h->start = (int *)h->dalloc(sizeof(int) * (nc + 1));
         h->bsum = (int *)h->dalloc(sizeof(int) * ((nc + kScanPerBlock - 1) / kScanPerBlock + 1));
         h->flags = (int *)h->dalloc(sizeof(int) * 4);
         h->stepc = (long long *)h->dalloc(sizeof(long long) * 2);
+        h->pt.need = (int *)h->dalloc(sizeof(int) * 4);
+        hip_check(hipMemsetAsync(h->pt.need, 0, sizeof(int) * 4, h->stream), "memset");
         h->diag_part = (double *)h->dalloc(sizeof(double) * 12 * 1024);
         h->diag_out = (double *)h->dalloc(sizeof(double) * 16);
         for (void *q : {h->df[0], h->df[1]}) hip_check(hipMemsetAsync(q, 0, rs * 19 * nc, h->stream), "memset");
         for (void *q : {h->drho, h->epsp}) hip_check(hipMemsetAsync(q, 0, rs * nc, h->stream), "memset");
-        for (void *q : {h->j, h->uprev, h->un, h->dudt, h->gradp, h->fam, h->facc})
+        for (void *q : {h->j, h->uprev, h->un, h->dudt, h->gradp, h->fam, h->uf, h->facc})
             hip_check(hipMemsetAsync(q, 0, rs * 3 * nc, h->stream), "memset");
         hip_check(hipMemsetAsync(h->cnt, 0, sizeof(int) * nc, h->stream), "memset");
         hip_check(hipMemsetAsync(h->start, 0, sizeof(int) * (nc + 1), h->stream), "memset");
@@ -772,6 +797,7 @@ lbdem_status lbdem_sync(lbdem_domain_t h)
             if (fl & FLAG_SKIN) m += " particle moved beyond the search skin within a subcycle;";
             if (fl & FLAG_NONFINITE) m += " non-finite particle state;";
             if (fl & FLAG_EPS) m += " fluid fraction <= 0;";
+            if (fl & FLAG_NLIST) m += " more neighbours within the interaction reach than the list holds;";
             return fail(h, LBDEM_E_UNSTABLE, m);
         }
         return LBDEM_OK;

@@ -28,7 +28,8 @@ struct Phys {
     double dt_int, dt_dem, c_am;
     double kn_per_m, xi_per_m;  // k_n / m_ij and xi_n / m_ij from T_c and e_n
     double skin;                // allowed displacement within one subcycle
-    int rbin;                   // DEM search radius in cells
+    double vskin;               // Verlet list skin
+    int rbin;                   // DEM search radius in cells (list build)
 };
 
 // Cell fields, [ncomp][nc] each. R = float (FP32 deviations) or double.
@@ -43,6 +44,7 @@ struct Cells {
     R *gradp;                   // [3] grad P
     R *epsp;                    // solid fraction 1 - eps_f of the current positions
     R *fam;                     // [3] -sum_p D F_am of the current subcycle
+    R *uf;                      // [3] u_f re-evaluated with f_ext = eps_f f_b + fam
     R *facc;                    // [3] subcycle mean of f_ext
 };
 
@@ -71,6 +73,11 @@ struct Parts {
     double *Fdem, *Tdem;        // contact + lubrication force and torque of the substep
     double *ustart, *xstart;    // velocity / position at subcycle start
     double *Fam_id, *Fd_id, *Fpr_id, *Fc_id;  // last subcycle's forces by insertion index
+    // Verlet lists by insertion index: nlist[id*kNbr + t], nnb[id] entries,
+    // built from positions xbuild[3][cap] (by id); slot_of[id] = current slot
+    int *nlist, *nnb, *slot_of;
+    double *xbuild;
+    int *need;                  // 1: rebuild the lists before the next DEM substep
 };
 
 struct Desc {
@@ -86,8 +93,11 @@ enum : int {
     FLAG_WALL = 1,              // particle centre through a wall
     FLAG_SKIN = 2,              // moved more than the skin within a subcycle
     FLAG_NONFINITE = 4,
-    FLAG_EPS = 8                // eps_f <= 0
+    FLAG_EPS = 8,               // eps_f <= 0
+    FLAG_NLIST = 16             // a particle has more than kNbr list neighbours
 };
+
+constexpr int kNbr = 80;        // Verlet list capacity per particle
 
 constexpr int kBlock = 256;
 constexpr int kScanItems = 8;   // per thread in the block scan
@@ -101,6 +111,7 @@ template <typename R> void launch_gather_am(const Desc &D, const Cells<R> &C, hi
 template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, int record, hipStream_t s);
 template <typename R> void launch_gather_fd(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_gather_eps_am(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s);
 template <typename R> void launch_to_double(const R *src, double *dst, int64_t n, hipStream_t s);
@@ -111,11 +122,13 @@ void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials
 int diag_blocks(const Desc &D);
 
 void launch_dem_force(const Desc &D, hipStream_t s);
+void launch_nlist(const Desc &D, hipStream_t s);      // rebuild Verlet lists if flagged
 void launch_integrate(const Desc &D, int last_substep, hipStream_t s);
 void launch_bin_count(const Desc &D, hipStream_t s);
 void launch_bin_build(const Desc &D, hipStream_t s);   // scan + place
 void launch_sort_permute(const Desc &D, hipStream_t s); // order bins, slots <- bin order, stencils
 void launch_zero_int(int *p, int64_t n, hipStream_t s);
 void launch_set_step(long long *stepc, long long v, hipStream_t s);
+void launch_set_int(int *p, int v, hipStream_t s);
 
 }  // namespace lbdem

@@ -281,6 +281,9 @@ __device__ __forceinline__ void load_stencil(const Parts &P, int64_t i, Stencil 
     }
 }
 
+// st.w[a][o] for a runtime o without indexing a register array
+__device__ __forceinline__ double sel3(const double w[3], int o) { return o == 0 ? w[0] : (o == 1 ? w[1] : w[2]); }
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
 {
@@ -301,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
             for (int ox = 0; ox < 3; ++ox) {
                 const int cx = stencil_coord(st.b[0], ox - 1, D.g.n[0], D.g.per[0]);
                 const int64_t cell = cidx(D.g, cx, cy, cz);
-                const double w = st.w[0][ox] * st.w[1][oy] * st.w[2][oz];
+                const double w = st.w[0][ox] * st.w[1][oy] * sel3(st.w[2], oz);
 #pragma unroll
                 for (int b = 0; b < 3; ++b) Du[b] += w * (double)C.dudt[b * nc + cell];
             }
@@ -393,14 +396,25 @@ __device__ __forceinline__ void gather_cell(const Desc &D, int i, int j, int k, 
 //   MODE_AM : fam  = -sum_p D F_am                    (Eq. forces_pf, added mass)
 //   MODE_FD : facc += (eps_f f_b + fam - sum_p D F_d) / n_int   (mean f_ext)
 //   MODE_EPS: epsp = sum_p D V_p                      (Eq. fluid_volume_fraction)
+//   MODE_EPS_AM: both of the new positions: the volume fraction at the end of
+//            one subcycle and the added-mass spreading of the next one
+// MODE_AM and MODE_EPS_AM also store the re-evaluated fluid-phase velocity
+// u_f = (j + (eps_f f_b + fam)/2) / (rho eps_f) (Sec. 3.2.3, Alg. 1).
 // ---------------------------------------------------------------------------
-enum { MODE_AM = 0, MODE_FD = 1, MODE_EPS = 2 };
+enum { MODE_AM = 0, MODE_FD = 1, MODE_EPS = 2, MODE_EPS_AM = 3 };
+
+template <int MODE> struct GatherNV { static constexpr int v = MODE == MODE_EPS ? 1 : (MODE == MODE_EPS_AM ? 4 : 3); };
 
 template <int MODE>
 __device__ __forceinline__ void gather_value(const Parts &P, int p, double *v)
 {
     if (MODE == MODE_EPS) {
         v[0] = sphere_volume(P.d[p]);
+    } else if (MODE == MODE_EPS_AM) {
+        v[0] = sphere_volume(P.d[p]);
+        v[1] = P.Fam[p];
+        v[2] = P.Fam[P.cap + p];
+        v[3] = P.Fam[2 * P.cap + p];
     } else {
         const double *F = MODE == MODE_AM ? P.Fam : P.Fd;
         v[0] = F[p];
@@ -409,13 +423,31 @@ __device__ __forceinline__ void gather_value(const Parts &P, int p, double *v)
     }
 }
 
+template <typename R>
+__device__ __forceinline__ void store_fam_uf(const Desc &D, const Cells<R> &C, int64_t c, double e, const double *sam)
+{
+    const int64_t nc = D.g.nc;
+    const double rho = 1.0 + (double)C.drho[c];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const R fam = (R)(-sam[b]);
+        C.fam[b * nc + c] = fam;
+        const double fext = e * D.p.fb[b] + (double)fam;
+        C.uf[b * nc + c] = (R)(((double)C.j[b * nc + c] + 0.5 * fext) / (rho * e));
+    }
+}
+
 template <typename R, int MODE>
 __device__ __forceinline__ void gather_store(const Desc &D, const Cells<R> &C, int64_t c, const double *s)
 {
     const int64_t nc = D.g.nc;
     if (MODE == MODE_AM) {
-#pragma unroll
-        for (int b = 0; b < 3; ++b) C.fam[b * nc + c] = (R)(-s[b]);
+        store_fam_uf<R>(D, C, c, 1.0 - (double)C.epsp[c], s);
+    } else if (MODE == MODE_EPS_AM) {
+        const double e = 1.0 - s[0];
+        if (!(e > 0.0) || !isfinite(e)) atomicOr(D.flags, FLAG_EPS);
+        C.epsp[c] = (R)s[0];
+        store_fam_uf<R>(D, C, c, 1.0 - (double)(R)s[0], s + 1);
     } else if (MODE == MODE_FD) {
         const double e = 1.0 - (double)C.epsp[c];
 #pragma unroll
@@ -434,7 +466,7 @@ template <typename R, int MODE, int TX, int TY, int TZ, int KMAX>
 __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
 {
     constexpr int NT = TX * TY * TZ, HX = TX + 2, HY = TY + 2, HZ = TZ + 2, NHB = HX * HY * HZ;
-    constexpr int NV = MODE == MODE_EPS ? 1 : 3;
+    constexpr int NV = GatherNV<MODE>::v;
     constexpr int PER = (NHB + NT - 1) / NT;
     __shared__ int hoff[NHB + 1];
     __shared__ int hsrc[NHB];
@@ -560,7 +592,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_cells(Desc D, Cells<R> C)
     if (c >= nc) return;
     int i, j, k;
     cell_coords(D.g, c, i, j, k);
-    constexpr int NV = MODE == MODE_EPS ? 1 : 3;
+    constexpr int NV = GatherNV<MODE>::v;
     double s[NV];
     gather_cell<NV>(D, i, j, k, [&](int p, double *v) { gather_value<MODE>(D.pt, p, v); }, s);
     gather_store<R, MODE>(D, C, c, s);
@@ -601,19 +633,13 @@ __global__ __launch_bounds__(kBlock) void k_part_drag(Desc D, Cells<R> C, int re
             for (int ox = 0; ox < 3; ++ox) {
                 const int cx = stencil_coord(st.b[0], ox - 1, D.g.n[0], D.g.per[0]);
                 const int64_t cell = cidx(D.g, cx, cy, cz);
-                const double w = st.w[0][ox] * st.w[1][oy] * st.w[2][oz];
-                const double epc = (double)C.epsp[cell];
-                const double e = 1.0 - epc;
-                const double rho = 1.0 + (double)C.drho[cell];
-                const double inv = 1.0 / (rho * e);
+                const double w = st.w[0][ox] * st.w[1][oy] * sel3(st.w[2], oz);
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
-                    const double fext = e * D.p.fb[b] + (double)C.fam[b * nc + cell];
-                    const double ub = ((double)C.j[b * nc + cell] + 0.5 * fext) * inv;
-                    uf[b] += w * ub;
+                    uf[b] += w * (double)C.uf[b * nc + cell];
                     gp[b] += w * (double)C.gradp[b * nc + cell];
                 }
-                ep += w * epc;
+                ep += w * (double)C.epsp[cell];
             }
         }
     }
@@ -778,12 +804,6 @@ __device__ __forceinline__ void load_pv(const Parts &P, int64_t i, PV &v)
     }
 }
 
-// Two phases per particle: the candidate scan only collects partners within
-// interaction reach into an LDS list; the force evaluation then runs over
-// that list, so lanes do not idle through each other's expensive pairs. If a
-// particle has more than kPBuf partners the scan is repeated for the rest.
-constexpr int kPBuf = 24;
-
 __device__ __forceinline__ void min_image(const Geo &g, double dx[3])
 {
 #pragma unroll
@@ -794,62 +814,95 @@ __device__ __forceinline__ void min_image(const Geo &g, double dx[3])
         }
 }
 
-__global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
+// Verlet lists (neighbour search for the sums of Eq. forces_collision,
+// Eq. torques_collision and Eq. lubrication_force, which only reach
+// (d_i + d_j)/2 + h_c). A list holds every particle within that reach plus a
+// skin, as insertion indices sorted ascending, so the force sums run in an
+// order that does not depend on when the list was built. Rebuilt only when a
+// particle has moved more than (skin/2 - per-subcycle limit) since the build.
+__global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
 {
-    __shared__ int nbr[kPBuf][kBlock];
-    const int64_t i = gidx();
     const Parts &P = D.pt;
+    if (*P.need == 0) return;
+    const int64_t i = gidx();
     if (i >= P.np) return;
     const int64_t cap = P.cap;
-    const int tid = threadIdx.x;
-    PV pi;
-    load_pv(P, i, pi);
-    double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
-    // bins were built from the subcycle-start positions
-    int b[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) b[a] = clampi((int)floor(P.xstart[a * cap + i]), 0, D.g.n[a] - 1);
+    const int me = P.id[i];
+    const double xi0 = P.x[i], xi1 = P.x[cap + i], xi2 = P.x[2 * cap + i];
+    const double ri = 0.5 * P.d[i];
+    const double gap = (D.p.use_lub ? fmax(D.p.h_c, 0.0) : 0.0) + D.p.vskin;
+    const int b0 = clampi((int)floor(xi0), 0, D.g.n[0] - 1);
+    const int b1 = clampi((int)floor(xi1), 0, D.g.n[1] - 1);
+    const int b2 = clampi((int)floor(xi2), 0, D.g.n[2] - 1);
     constexpr int kMaxR = 8;
     int cx[2 * kMaxR + 1], cy[2 * kMaxR + 1], cz[2 * kMaxR + 1];
     const int R = D.p.rbin;
-    const double reach_gap = D.p.use_lub ? fmax(D.p.h_c, 0.0) : 0.0;
-    const int mx = axis_range(b[0], R, D.g.n[0], D.g.per[0], cx, 2 * kMaxR + 1);
-    const int my = axis_range(b[1], R, D.g.n[1], D.g.per[1], cy, 2 * kMaxR + 1);
-    const int mz = axis_range(b[2], R, D.g.n[2], D.g.per[2], cz, 2 * kMaxR + 1);
-    // slots are sorted by cell: a non-wrapping x-row of bins is one slot range
+    const int mx = axis_range(b0, R, D.g.n[0], D.g.per[0], cx, 2 * kMaxR + 1);
+    const int my = axis_range(b1, R, D.g.n[1], D.g.per[1], cy, 2 * kMaxR + 1);
+    const int mz = axis_range(b2, R, D.g.n[2], D.g.per[2], cz, 2 * kMaxR + 1);
     const bool run = mx >= 1 && cx[mx - 1] - cx[0] == mx - 1;
     const int nrun = run ? 1 : mx;
-    int skip = 0;
-    bool more = true;
-    while (more) {
-        more = false;
-        int m = 0, seen = 0;
-        for (int c2 = 0; c2 < mz; ++c2)
-            for (int c1 = 0; c1 < my; ++c1)
-                for (int c0 = 0; c0 < nrun; ++c0) {
-                    const int64_t bin = cidx(D.g, cx[c0], cy[c1], cz[c2]);
-                    const int p0 = D.b.start[bin];
-                    const int p1 = D.b.start[bin + (run ? mx : 1)];
-                    for (int jdx = p0; jdx < p1; ++jdx) {
-                        if (jdx == i) continue;
-                        double dx[3] = {P.x[jdx] - pi.x[0], P.x[cap + jdx] - pi.x[1], P.x[2 * cap + jdx] - pi.x[2]};
-                        min_image(D.g, dx);
-                        const double reach = pi.r + 0.5 * P.d[jdx] + reach_gap;
-                        if (dot3(dx, dx) >= reach * reach) continue;
-                        if (seen++ < skip) continue;
-                        if (m < kPBuf) nbr[m++][tid] = jdx;
-                        else more = true;
+    int *L = P.nlist + (int64_t)me * kNbr;
+    int m = 0;
+    for (int c2 = 0; c2 < mz; ++c2)
+        for (int c1 = 0; c1 < my; ++c1)
+            for (int c0 = 0; c0 < nrun; ++c0) {
+                const int64_t bin = cidx(D.g, cx[c0], cy[c1], cz[c2]);
+                const int p0 = D.b.start[bin];
+                const int p1 = D.b.start[bin + (run ? mx : 1)];
+                for (int j = p0; j < p1; ++j) {
+                    if (j == i) continue;
+                    double dx[3] = {P.x[j] - xi0, P.x[cap + j] - xi1, P.x[2 * cap + j] - xi2};
+                    min_image(D.g, dx);
+                    const double reach = ri + 0.5 * P.d[j] + gap;
+                    if (dot3(dx, dx) >= reach * reach) continue;
+                    if (m < kNbr) {
+                        // insertion by ascending insertion index
+                        const int v = P.id[j];
+                        int t = m - 1;
+                        while (t >= 0 && L[t] > v) {
+                            L[t + 1] = L[t];
+                            --t;
+                        }
+                        L[t + 1] = v;
                     }
+                    ++m;
                 }
-        for (int t = 0; t < m; ++t) {
-            const int jdx = nbr[t][tid];
-            PV pj;
-            load_pv(P, jdx, pj);
-            double dx[3] = {pj.x[0] - pi.x[0], pj.x[1] - pi.x[1], pj.x[2] - pi.x[2]};
-            min_image(D.g, dx);
-            pair_interaction(D.p, pi, pj, dx, F, T);
-        }
-        skip += m;
+            }
+    if (m > kNbr) {
+        atomicOr(D.flags, FLAG_NLIST);
+        m = kNbr;
+    }
+    P.nnb[me] = m;
+    P.xbuild[me] = xi0;
+    P.xbuild[cap + me] = xi1;
+    P.xbuild[2 * cap + me] = xi2;
+}
+
+// contact + lubrication force and torque on every particle from its list
+__global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
+{
+    const Parts &P = D.pt;
+    const int64_t i = gidx();
+    if (i == 0) *P.need = 0;  // lists are current for this subcycle
+    if (i >= P.np) return;
+    const int64_t cap = P.cap;
+    PV pi;
+    load_pv(P, i, pi);
+    double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+    const double gap = D.p.use_lub ? fmax(D.p.h_c, 0.0) : 0.0;
+    const int me = P.id[i];
+    const int n = P.nnb[me];
+    const int *L = P.nlist + (int64_t)me * kNbr;
+    for (int t = 0; t < n; ++t) {
+        const int j = P.slot_of[L[t]];
+        double dx[3] = {P.x[j] - pi.x[0], P.x[cap + j] - pi.x[1], P.x[2 * cap + j] - pi.x[2]};
+        min_image(D.g, dx);
+        const double reach = pi.r + 0.5 * P.d[j] + gap;
+        if (dot3(dx, dx) >= reach * reach) continue;
+        PV pj;
+        load_pv(P, j, pj);
+        pair_interaction(D.p, pi, pj, dx, F, T);
     }
     wall_interaction(D.p, D.g, pi, F, T);
 #pragma unroll
@@ -873,6 +926,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(Desc D, int last)
     const double dt = D.p.dt_dem;
     double x[3];
     int bad = 0;
+    double moved = 0.0;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int64_t k = a * cap + i;
@@ -897,8 +951,16 @@ __global__ __launch_bounds__(kBlock) void k_integrate(Desc D, int last)
         if (D.g.per[a]) dx -= L * rint(dx / L);
         if (fabs(dx) > D.p.skin) bad |= FLAG_SKIN;
         if (last) P.a[k] = (u - P.ustart[k]) / D.p.dt_int;
+        if (last) {
+            double db = xa - P.xbuild[a * cap + P.id[i]];
+            if (D.g.per[a]) db -= L * rint(db / L);
+            moved = fmax(moved, fabs(db));
+        }
     }
     if (bad) atomicOr(D.flags, bad);
+    // with at most `skin` per subcycle, rebuilding once any particle has moved
+    // vskin/2 - skin keeps every pair within the list reach until the rebuild
+    if (last && moved > 0.5 * D.p.vskin - D.p.skin) *P.need = 1;
     if (last) atomicAdd(&D.b.cnt[particle_cell(D.g, x[0], x[1], x[2])], 1);
 }
 
@@ -1039,7 +1101,9 @@ __global__ __launch_bounds__(kBlock) void k_permute(Desc D)
     }
     P.d2[s] = P.d[src];
     P.rho2[s] = P.rho[src];
-    P.id2[s] = P.id[src];
+    const int pid = P.id[src];
+    P.id2[s] = pid;
+    P.slot_of[pid] = (int)s;
 }
 
 // ---------------------------------------------------------------------------
@@ -1193,6 +1257,7 @@ __global__ void k_convert(const A *src, B *dst, int64_t n)
 }
 
 __global__ void k_set_step(long long *s, long long v) { *s = v; }
+__global__ void k_set_int(int *p, int v) { *p = v; }
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -1256,6 +1321,10 @@ template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, h
 {
     launch_gather<R, MODE_EPS>(D, C, s);
 }
+template <typename R> void launch_gather_eps_am(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    launch_gather<R, MODE_EPS_AM>(D, C, s);
+}
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
     hipLaunchKernelGGL(k_stream_collide<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
@@ -1293,6 +1362,10 @@ void launch_dem_force(const Desc &D, hipStream_t s)
 {
     if (D.pt.np > 0) hipLaunchKernelGGL(k_dem_force, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
 }
+void launch_nlist(const Desc &D, hipStream_t s)
+{
+    if (D.pt.np > 0) hipLaunchKernelGGL(k_nlist, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+}
 void launch_integrate(const Desc &D, int last, hipStream_t s)
 {
     if (D.pt.np > 0) hipLaunchKernelGGL(k_integrate, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, last);
@@ -1315,6 +1388,10 @@ void launch_sort_permute(const Desc &D, hipStream_t s)
     if (D.pt.np > 0) hipLaunchKernelGGL(k_permute, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
 }
 void launch_zero_int(int *p, int64_t n, hipStream_t s) { launch_zero<int>(p, n, s); }
+void launch_set_int(int *p, int v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
+}
 void launch_set_step(long long *stepc, long long v, hipStream_t s)
 {
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, s, stepc, v);
@@ -1328,6 +1405,7 @@ void launch_set_step(long long *stepc, long long v, hipStream_t s)
     template void launch_part_drag<R>(const Desc &, const Cells<R> &, int, hipStream_t);                        \
     template void launch_gather_fd<R>(const Desc &, const Cells<R> &, hipStream_t);                        \
     template void launch_gather_eps<R>(const Desc &, const Cells<R> &, hipStream_t);                       \
+    template void launch_gather_eps_am<R>(const Desc &, const Cells<R> &, hipStream_t);                    \
     template void launch_stream_collide<R>(const Desc &, const Cells<R> &, hipStream_t);                   \
     template void launch_zero<R>(R *, int64_t, hipStream_t);                                                \
     template void launch_to_double<R>(const R *, double *, int64_t, hipStream_t);                          \
