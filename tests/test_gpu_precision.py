@@ -1,0 +1,121 @@
+"""FP32-deviation storage vs the FP64 oracle, and full-size parity.
+
+Tolerances of the FP32 path (PDFs and cell fields as float deviations from
+the rest weights; particle integration and reductions FP64), on the dilute
+settling workload shape after 200 coupled steps from rest:
+  * mean relative settling velocity <u_pS> (Sec. 4.1), averaged over the
+    last 100 steps:                                      1e-3 relative
+  * mean porosity <eps_f>:                               1e-6 relative
+  * total momentum sum_x j + sum_p m u_p:                1e-6 of the momentum
+    moved: sum_p m |u_p| + sum_x |j| + steps |f_b| N_c
+and, for one step from an identical state, every state array within 1e-5 of
+its largest oracle value (FP32 rounding of O(1e-7) deviations).
+
+The momentum scale includes the body-force impulse because the total
+momentum of a periodic settling box is only the small residual of the fluid
+body force and the particles' submerged weight (Sec. 4.1 Setup); FP32 rounds
+the uniform force density identically in every cell, an error proportional
+to the injected impulse, not to the residual.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1711_00336_amd import inputs as I
+from tests.parity_util import compare_states, load_oracle_state, warm_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL32_STEP = 1e-5
+TOL_UPS, TOL_EPS, TOL_MOM = 1e-3, 1e-6, 1e-6
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1711_00336_amd import lbdem
+    lbdem.lib()
+    return lbdem
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def test_fp32_one_step_vs_oracle(L):
+    case = I.case_settling(9, 24, 0.1, 0.8, 2.5, precision="fp32dev")
+    _say(f"case {case.name} np {case.particles.n}")
+    o = warm_oracle(case, 3)
+    with L.Domain(case.params) as dom:
+        load_oracle_state(dom, o.state)
+        dom.step(1)
+        o.step(1)
+        errs, bad = compare_states(dom.lbdem_get_state(), o.state, case.params, TOL32_STEP)
+    _say(f"  fp32 one-step rel errors {errs}")
+    assert not bad, errs
+
+
+def _momentum(d, L=None):
+    return np.asarray(d["mom_fluid"]) + np.asarray(d["mom_part"])
+
+
+def test_fp32_settling_observables(L):
+    """200 steps from rest, FP32 GPU vs FP64 oracle: settling velocity,
+    porosity and total momentum within the stated tolerances."""
+    case = I.case_settling(3, 40, 0.05, 0.8, 2.5, precision="fp32dev")
+    nsteps, avg_from = 200, 100
+    _say(f"case {case.name} np {case.particles.n} steps {nsteps}")
+    o = O.Oracle(case.params, case.particles)
+    ups_o, ups_g = [], []
+    with L.Domain(case.params) as dom:
+        dom.add(case.particles)
+        for s in range(nsteps):
+            dom.step(1)
+            r = o.step(1)
+            assert r["status"] == 0
+            if s >= avg_from:
+                ups_o.append(o.diagnostics()["u_ps"])
+                ups_g.append(dom.lbdem_diagnostics()["u_ps"])
+        dg = dom.lbdem_diagnostics()
+        g = dom.lbdem_get_state()
+    do = o.diagnostics()
+    ups_o, ups_g = float(np.mean(ups_o)), float(np.mean(ups_g))
+    m = g["rho_p"] * np.pi * g["d"] ** 3 / 6
+    nc = case.params.n[0] * case.params.n[1] * case.params.n[2]
+    scale = float(np.sum(m[:, None] * np.abs(o.state.u)) + np.sum(np.abs(do["mom_fluid"]))
+                  + nsteps * np.abs(np.asarray(o.fb)).max() * nc)
+    e_ups = abs(ups_g - ups_o) / abs(ups_o)
+    e_eps = abs(dg["mean_eps_f"] - do["mean_eps_f"]) / do["mean_eps_f"]
+    e_mom = float(np.abs(_momentum(dg) - _momentum(do)).max()) / scale
+    _say(f"  <u_pS> gpu {ups_g:.6e} oracle {ups_o:.6e} rel {e_ups:.2e}; <eps_f> rel {e_eps:.2e}; momentum rel {e_mom:.2e}")
+    assert e_ups <= TOL_UPS and e_eps <= TOL_EPS and e_mom <= TOL_MOM
+
+
+def test_fp64_free_running_drift(L):
+    """FP64 GPU and oracle advanced independently for 40 steps from the same
+    initial state stay within 1e-10 (chaotic growth of round-off differences
+    is slow in this dilute walled case)."""
+    case = I.case_small_walled(7)
+    o = O.Oracle(case.params, case.particles)
+    with L.Domain(case.params) as dom:
+        dom.add(case.particles)
+        dom.step(40)
+        o.step(40)
+        errs, bad = compare_states(dom.lbdem_get_state(), o.state, case.params, 1e-10)
+    _say(f"  40-step drift {errs}")
+    assert not bad, errs
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32dev", TOL32_STEP)])
+def test_full_size_dilute_one_step(L, precision, tol):
+    """The benchmark workload at full size (128^3 cells, 391,139 spheres), one
+    coupled step from an identical oracle state."""
+    case = I.case_dilute_periodic(0, n=128, eps_p=0.05, d=0.8, precision=precision)
+    _say(f"case {case.name} {precision} np {case.particles.n}")
+    o = warm_oracle(case, 1)
+    with L.Domain(case.params) as dom:
+        load_oracle_state(dom, o.state)
+        dom.step(1)
+        o.step(1)
+        errs, bad = compare_states(dom.lbdem_get_state(), o.state, case.params, tol)
+    _say(f"  full-size rel errors {errs}")
+    assert not bad, errs
