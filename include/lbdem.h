@@ -192,6 +192,85 @@ lbdem_status lbdem_load_state(lbdem_domain_t h, const void *blob, size_t size);
 lbdem_status lbdem_set_timing(lbdem_domain_t h, int on);
 lbdem_status lbdem_kernel_time(lbdem_domain_t h, int cls, double *ms_total, int64_t *launches);
 
+/* Pick launch shapes for this domain by timing them on its current state
+ * (gather tile shape; results are bit-identical across choices). Optional
+ * out: the chosen tile variant (0 16x4x4, 1 8x4x4, 2 8x8x4). */
+lbdem_status lbdem_autotune(lbdem_domain_t h, int32_t *gather_variant);
+
+/* ---- Batching: many independent domains (e.g. a parameter sweep of the
+ * settling problem of Sec. 4.1) advanced together. One batch step replays a
+ * single captured HIP graph that runs every domain's full coupled step, the
+ * domains spread over parallel branches. */
+typedef struct lbdem_batch *lbdem_batch_t;
+
+/* n domains from p[0..n-1] (each validated as in lbdem_create), sharing one
+ * stream (hip_stream, NULL: created). Errors: lbdem_last_error(NULL). */
+lbdem_status lbdem_batch_create(int32_t n, const lbdem_params *p, void *hip_stream, lbdem_batch_t *out);
+
+/* Handle of domain i, owned by the batch (not to be destroyed): use it with
+ * lbdem_add_particles, lbdem_read_*, lbdem_diagnostics, lbdem_get_state. */
+lbdem_status lbdem_batch_domain(lbdem_batch_t b, int32_t i, lbdem_domain_t *out);
+int32_t lbdem_batch_size(lbdem_batch_t b);
+
+/* Run lbdem_autotune on every domain. */
+lbdem_status lbdem_batch_autotune(lbdem_batch_t b);
+
+/* Enqueue nsteps coupled steps of every domain (asynchronous). */
+lbdem_status lbdem_batch_step(lbdem_batch_t b, int64_t nsteps);
+
+/* Wait; E_UNSTABLE if any domain flagged instability (message names it). */
+lbdem_status lbdem_batch_sync(lbdem_batch_t b);
+
+lbdem_status lbdem_batch_destroy(lbdem_batch_t b);
+
+/* ---- Serving: a request loop for settling solves (the problem of
+ * Sec. 4.1) of different sizes and solid fractions. A background thread
+ * admits queued requests first-come-first-served while their device
+ * footprint fits the HBM budget and a slot is free, keeps admitted domains
+ * resident, and advances all of them chunk_steps at a time on parallel
+ * streams; requests arriving meanwhile join at the next chunk boundary. */
+typedef struct lbdem_server *lbdem_server_t;
+
+typedef struct lbdem_request {
+    lbdem_params params;      /* the domain (as for lbdem_create) */
+    int64_t np;               /* particles, host arrays copied at submit: */
+    const double *x, *u, *omega;  /* [np][3] (u, omega may be NULL: at rest) */
+    const double *d, *rho_p;      /* [np] */
+    int64_t steps;            /* coupled steps to run (>= 1) */
+    int64_t avg_from;         /* <u_pS> is averaged over chunk ends after this step */
+} lbdem_request;
+
+typedef struct lbdem_result {
+    int32_t status;           /* LBDEM_OK, the failing call's status, or E_STATE if cancelled */
+    int64_t steps_done;
+    double u_ps;              /* mean relative settling velocity (Sec. 4.1), time-averaged */
+    double mean_eps_f;        /* <eps_f> at the end */
+    double mom[3];            /* total momentum at the end */
+    double t_submit, t_admit, t_done;  /* seconds on the server's clock */
+} lbdem_result;
+
+/* Message of the last failed server call of this thread. */
+const char *lbdem_server_last_error(void);
+
+/* Start a server on the current device: hbm_budget bytes for resident
+ * domains, at most max_slots resident at once, chunk_steps per scheduling
+ * round. */
+lbdem_status lbdem_server_create(size_t hbm_budget, int32_t max_slots, int32_t chunk_steps, lbdem_server_t *out);
+
+/* Queue a request; E_INVALID if it can never fit the budget. */
+lbdem_status lbdem_server_submit(lbdem_server_t s, const lbdem_request *r, uint64_t *ticket);
+
+/* LBDEM_OK with the result once the solve has finished, else LBDEM_E_BUSY. */
+lbdem_status lbdem_server_poll(lbdem_server_t s, uint64_t ticket, lbdem_result *out);
+
+/* Cancel a queued or running request (its result reports E_STATE). */
+lbdem_status lbdem_server_cancel(lbdem_server_t s, uint64_t ticket);
+
+lbdem_status lbdem_server_stats(lbdem_server_t s, int64_t *queued, int64_t *active, size_t *bytes_in_use);
+
+/* Stop the loop, free every resident domain. */
+lbdem_status lbdem_server_destroy(lbdem_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

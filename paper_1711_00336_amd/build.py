@@ -25,7 +25,8 @@ ARCH = "gfx950"
 DEVICE_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]
-HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
+HOST_FLAGS = ["-O2", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
 
 
 def _run(cmd):
@@ -44,12 +45,13 @@ def build(verbose: bool = False) -> str:
     ko = os.path.join(OUT_DIR, "lbdem_kernels.o")
     _run([HIPCC, *DEVICE_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", kern, "-o", ko])
     objs.append(ko)
-    capi = os.path.join(CSRC, "lbdem_capi.cpp")
-    co = os.path.join(OUT_DIR, "lbdem_capi.o")
-    _run([HIPCC, *HOST_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", capi, "-o", co])
-    objs.append(co)
+    for name in ("lbdem_capi", "lbdem_server"):
+        src = os.path.join(CSRC, name + ".cpp")
+        obj = os.path.join(OUT_DIR, name + ".o")
+        _run([HIPCC, *HOST_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj])
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs])
+    _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs, "-lpthread"])
     os.replace(tmp, LIB)
     for o in objs:
         os.remove(o)

@@ -52,6 +52,8 @@ struct lbdem_domain {
     int prec = LBDEM_FP64;
     Geo geo{};
     Phys phys{};
+    Tune tune{-1};
+    int64_t version = 0;        // bumped whenever the particle set is replaced
     std::string err;
     int64_t step_host = 0;
 
@@ -132,6 +134,7 @@ struct lbdem_domain {
         Desc D{};
         D.g = geo;
         D.p = phys;
+        D.t = tune;
         D.b = Bins{cnt, start, list, bsum};
         D.pt = pt;
         D.flags = flags;
@@ -460,6 +463,7 @@ HostParticles fetch_particles(lbdem_domain_t h)
 void put_particles(lbdem_domain_t h, const HostParticles &hp)
 {
     h->drop_graphs();
+    h->version += 1;
     const int64_t n = (int64_t)hp.d.size();
     if (n > h->pt.cap) alloc_particles(h, std::max<int64_t>(n, 2 * h->pt.cap));
     h->pt.np = n;
@@ -1036,6 +1040,58 @@ lbdem_status lbdem_load_state(lbdem_domain_t h, const void *blob, size_t size)
     return lbdem_set_state(h, &v);
 }
 
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// autotuner: time the gather tile variants on the domain's current state
+// with the volume-fraction gather (idempotent: it rewrites the same field)
+// and keep the fastest. Variants give bit-identical results.
+// --------------------------------------------------------------------------
+template <typename R>
+static void autotune_impl(lbdem_domain_t h)
+{
+    hipEvent_t a, b;
+    hip_check(hipEventCreate(&a), "hipEventCreate");
+    hip_check(hipEventCreate(&b), "hipEventCreate");
+    float best = 1e30f;
+    int best_v = 0;
+    for (int v = 0; v < kGatherVariants; ++v) {
+        h->tune.gather = v;
+        float tmin = 1e30f;
+        for (int rep = 0; rep < 4; ++rep) {
+            hip_check(hipEventRecord(a, h->stream), "hipEventRecord");
+            launch_gather_eps<R>(h->desc(), h->cells<R>(), h->stream);
+            hip_check(hipEventRecord(b, h->stream), "hipEventRecord");
+            hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+            if (rep > 0) tmin = std::min(tmin, ms);
+        }
+        if (tmin < best) {
+            best = tmin;
+            best_v = v;
+        }
+    }
+    h->tune.gather = best_v;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    h->drop_graphs();
+}
+
+extern "C" {
+
+lbdem_status lbdem_autotune(lbdem_domain_t h, int32_t *gather_variant)
+{
+    if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
+    return guarded(h, [&]() -> lbdem_status {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        if (h->prec == LBDEM_FP64) autotune_impl<double>(h);
+        else autotune_impl<float>(h);
+        if (gather_variant) *gather_variant = h->tune.gather;
+        return LBDEM_OK;
+    });
+}
+
 lbdem_status lbdem_set_timing(lbdem_domain_t h, int on)
 {
     if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
@@ -1061,6 +1117,194 @@ lbdem_status lbdem_kernel_time(lbdem_domain_t h, int cls, double *ms_total, int6
         if (launches) *launches = h->cls_n[cls];
         return LBDEM_OK;
     });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batching: independent domains advanced together. One batch step is a
+// single captured HIP graph whose branches (one per worker stream) each run
+// the full step of a share of the domains, so small domains overlap on the
+// device. Domains keep their own parameters (n_int, precision, tuning).
+// ===========================================================================
+struct lbdem_batch {
+    std::vector<lbdem_domain_t> doms;
+    hipStream_t master = nullptr;
+    bool own_master = false;
+    std::vector<hipStream_t> workers;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+    std::vector<std::pair<std::string, hipGraphExec_t>> graphs;
+    bool tuned = false;
+};
+
+namespace {
+
+std::string batch_key(lbdem_batch_t b)
+{
+    std::string k;
+    for (lbdem_domain_t d : b->doms)
+        k += std::to_string(d->cur) + ":" + std::to_string(d->pswap) + ":" + std::to_string(d->version) + ";";
+    return k;
+}
+
+void advance_bookkeeping(lbdem_domain_t d, int dir)
+{
+    d->cur ^= 1;
+    d->step_host += dir;
+    if (d->phys.n_int & 1) swap_particle_buffers(d);
+}
+
+void batch_drop_graphs(lbdem_batch_t b)
+{
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.second);
+    b->graphs.clear();
+}
+
+void batch_enqueue(lbdem_batch_t b)
+{
+    const int S = (int)b->workers.size();
+    hip_check(hipEventRecord(b->fork, b->master), "hipEventRecord");
+    for (hipStream_t w : b->workers) hip_check(hipStreamWaitEvent(w, b->fork, 0), "hipStreamWaitEvent");
+    for (size_t i = 0; i < b->doms.size(); ++i) {
+        lbdem_domain_t d = b->doms[i];
+        hipStream_t saved = d->stream;
+        d->stream = b->workers[i % S];
+        try {
+            if (d->prec == LBDEM_FP64) enqueue_step<double>(d);
+            else enqueue_step<float>(d);
+        } catch (...) {
+            d->stream = saved;
+            throw;
+        }
+        d->stream = saved;
+    }
+    for (int w = 0; w < S; ++w) {
+        hip_check(hipEventRecord(b->join[w], b->workers[w]), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(b->master, b->join[w], 0), "hipStreamWaitEvent");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+lbdem_status lbdem_batch_create(int32_t n, const lbdem_params *p, void *hip_stream, lbdem_batch_t *out)
+{
+    if (!p || !out || n < 1) return fail(nullptr, LBDEM_E_INVALID, "bad batch arguments");
+    *out = nullptr;
+    lbdem_batch_t b = new lbdem_batch();
+    lbdem_status st = guarded(nullptr, [&]() -> lbdem_status {
+        if (hip_stream) b->master = (hipStream_t)hip_stream;
+        else {
+            hip_check(hipStreamCreateWithFlags(&b->master, hipStreamNonBlocking), "hipStreamCreate");
+            b->own_master = true;
+        }
+        const int S = std::min<int>(n, 4);
+        for (int w = 0; w < S; ++w) {
+            hipStream_t s;
+            hip_check(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+            b->workers.push_back(s);
+            hipEvent_t e;
+            hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+            b->join.push_back(e);
+        }
+        hip_check(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "hipEventCreate");
+        for (int i = 0; i < n; ++i) {
+            lbdem_domain_t d = nullptr;
+            lbdem_status s2 = lbdem_create(&p[i], (void *)b->master, &d);
+            if (s2 != LBDEM_OK)
+                return fail(nullptr, s2, "domain " + std::to_string(i) + ": " + g_thread_err);
+            b->doms.push_back(d);
+        }
+        return LBDEM_OK;
+    });
+    if (st != LBDEM_OK) {
+        lbdem_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return LBDEM_OK;
+}
+
+lbdem_status lbdem_batch_domain(lbdem_batch_t b, int32_t i, lbdem_domain_t *out)
+{
+    if (!b || !out || i < 0 || i >= (int32_t)b->doms.size()) return fail(nullptr, LBDEM_E_INVALID, "bad domain index");
+    *out = b->doms[i];
+    return LBDEM_OK;
+}
+
+lbdem_status lbdem_batch_autotune(lbdem_batch_t b)
+{
+    if (!b) return fail(nullptr, LBDEM_E_INVALID, "null batch");
+    for (size_t i = 0; i < b->doms.size(); ++i) {
+        lbdem_status st = lbdem_autotune(b->doms[i], nullptr);
+        if (st != LBDEM_OK) return fail(nullptr, st, "domain " + std::to_string(i) + ": " + b->doms[i]->err);
+    }
+    batch_drop_graphs(b);
+    b->tuned = true;
+    return LBDEM_OK;
+}
+
+lbdem_status lbdem_batch_step(lbdem_batch_t b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return fail(nullptr, LBDEM_E_INVALID, "bad batch step arguments");
+    return guarded(nullptr, [&]() -> lbdem_status {
+        for (int64_t s = 0; s < nsteps; ++s) {
+            const std::string key = batch_key(b);
+            hipGraphExec_t ge = nullptr;
+            for (auto &g : b->graphs)
+                if (g.first == key) ge = g.second;
+            if (!ge) {
+                hipGraph_t g = nullptr;
+                hip_check(hipStreamBeginCapture(b->master, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+                try {
+                    batch_enqueue(b);
+                } catch (...) {
+                    hipGraph_t dummy = nullptr;
+                    (void)hipStreamEndCapture(b->master, &dummy);
+                    if (dummy) (void)hipGraphDestroy(dummy);
+                    throw;
+                }
+                hip_check(hipStreamEndCapture(b->master, &g), "hipStreamEndCapture");
+                for (lbdem_domain_t d : b->doms) advance_bookkeeping(d, -1);
+                hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                hip_check(e, "hipGraphInstantiate");
+                if (b->graphs.size() >= 4) batch_drop_graphs(b);
+                b->graphs.emplace_back(key, ge);
+            }
+            hip_check(hipGraphLaunch(ge, b->master), "hipGraphLaunch");
+            for (lbdem_domain_t d : b->doms) advance_bookkeeping(d, +1);
+        }
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_batch_sync(lbdem_batch_t b)
+{
+    if (!b) return fail(nullptr, LBDEM_E_INVALID, "null batch");
+    for (size_t i = 0; i < b->doms.size(); ++i) {
+        lbdem_status st = lbdem_sync(b->doms[i]);
+        if (st != LBDEM_OK) return fail(nullptr, st, "domain " + std::to_string(i) + ": " + b->doms[i]->err);
+    }
+    return LBDEM_OK;
+}
+
+int32_t lbdem_batch_size(lbdem_batch_t b) { return b ? (int32_t)b->doms.size() : 0; }
+
+lbdem_status lbdem_batch_destroy(lbdem_batch_t b)
+{
+    if (!b) return LBDEM_OK;
+    if (b->master) (void)hipStreamSynchronize(b->master);
+    batch_drop_graphs(b);
+    for (lbdem_domain_t d : b->doms) lbdem_destroy(d);
+    for (hipStream_t s : b->workers) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : b->join) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->own_master && b->master) (void)hipStreamDestroy(b->master);
+    delete b;
+    return LBDEM_OK;
 }
 
 }  // extern "C"

@@ -80,9 +80,15 @@ struct Parts {
     int *need;                  // 1: rebuild the lists before the next DEM substep
 };
 
+// launch choices picked per domain (autotuner); -1 = heuristic default
+struct Tune {
+    int gather;                 // gather tile: 0 16x4x4, 1 8x4x4, 2 8x8x4
+};
+
 struct Desc {
     Geo g;
     Phys p;
+    Tune t;
     Bins b;
     Parts pt;
     int *flags;                 // error bits
@@ -112,6 +118,7 @@ template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, in
 template <typename R> void launch_gather_fd(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_eps_am(const Desc &D, const Cells<R> &C, hipStream_t s);
+constexpr int kGatherVariants = 3;
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s);
 template <typename R> void launch_to_double(const R *src, double *dst, int64_t n, hipStream_t s);

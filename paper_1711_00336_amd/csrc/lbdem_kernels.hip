@@ -1286,9 +1286,10 @@ template <typename R> void launch_part_am(const Desc &D, const Cells<R> &C, hipS
 {
     if (D.pt.np > 0) hipLaunchKernelGGL(k_part_am<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
 }
-// tile shapes: a dilute variant (16x4x4 cells, up to 384 staged particles)
-// and a dense one (8x4x4, up to 512); periodic axes thinner than 3 cells use
-// the per-cell gather
+// tile shapes (chosen per domain by the autotuner, else by particle density):
+// 0: 16x4x4 cells, up to 384 staged particles; 1: 8x4x4, 512; 2: 8x8x4, 512.
+// All give bit-identical results: every cell sums its bins in the same order.
+// Periodic axes thinner than 3 cells use the per-cell gather.
 template <typename R, int MODE> void launch_gather(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
     const bool thin = (D.g.per[0] && D.g.n[0] < 3) || (D.g.per[1] && D.g.n[1] < 3) || (D.g.per[2] && D.g.n[2] < 3);
@@ -1296,13 +1297,20 @@ template <typename R, int MODE> void launch_gather(const Desc &D, const Cells<R>
         hipLaunchKernelGGL((k_gather_cells<R, MODE>), dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
         return;
     }
-    const double density = D.g.nc > 0 ? (double)D.pt.np / (double)D.g.nc : 0.0;
-    if (density < 0.3) {
+    int v = D.t.gather;
+    if (v < 0 || v >= kGatherVariants) {
+        const double density = D.g.nc > 0 ? (double)D.pt.np / (double)D.g.nc : 0.0;
+        v = density < 0.3 ? 0 : 1;
+    }
+    if (v == 0) {
         dim3 grid((D.g.n[0] + 15) / 16, (D.g.n[1] + 3) / 4, (D.g.n[2] + 3) / 4);
         hipLaunchKernelGGL((k_gather_tile<R, MODE, 16, 4, 4, 384>), grid, dim3(256), 0, s, D, C);
-    } else {
+    } else if (v == 1) {
         dim3 grid((D.g.n[0] + 7) / 8, (D.g.n[1] + 3) / 4, (D.g.n[2] + 3) / 4);
         hipLaunchKernelGGL((k_gather_tile<R, MODE, 8, 4, 4, 512>), grid, dim3(128), 0, s, D, C);
+    } else {
+        dim3 grid((D.g.n[0] + 7) / 8, (D.g.n[1] + 7) / 8, (D.g.n[2] + 3) / 4);
+        hipLaunchKernelGGL((k_gather_tile<R, MODE, 8, 8, 4, 512>), grid, dim3(256), 0, s, D, C);
     }
 }
 template <typename R> void launch_gather_am(const Desc &D, const Cells<R> &C, hipStream_t s)

@@ -1,0 +1,127 @@
+/*
+ * Geometric overlap removal for the seeded sphere packings of inputs.py.
+ * Not part of the method: overlapping pairs are pushed apart along their
+ * centre line by half the overlap each (Gauss-Seidel sweeps over a cell
+ * list), walls clamp centres to [r, L - r], periodic axes wrap.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static double wrapd(double x, double L)
+{
+    if (x >= L) x -= L * floor(x / L);
+    else if (x < 0.0) x -= L * floor(x / L);
+    if (x >= L) x = 0.0;
+    return x;
+}
+
+/* returns the number of sweeps used, or -1 if max_sweeps was reached */
+int lbdem_inputs_relax(int64_t n, double *pos, const double *r, const double *box, const int32_t *per,
+                       double tol, int32_t max_sweeps)
+{
+    if (n <= 1) return 0;
+    double rmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) rmax = fmax(rmax, r[i]);
+    int nb[3];
+    double cs[3];
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; ++a) {
+        nb[a] = (int)floor(box[a] / (2.0 * rmax));
+        if (nb[a] < 1) nb[a] = 1;
+        cs[a] = box[a] / nb[a];
+        ncell *= nb[a];
+    }
+    int64_t *start = malloc(sizeof(int64_t) * (size_t)(ncell + 1));
+    int64_t *cnt = malloc(sizeof(int64_t) * (size_t)ncell);
+    int64_t *order = malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *cell = malloc(sizeof(int64_t) * (size_t)n);
+    int result = -1;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        memset(cnt, 0, sizeof(int64_t) * (size_t)ncell);
+        for (int64_t i = 0; i < n; ++i) {
+            int b[3];
+            for (int a = 0; a < 3; ++a) {
+                b[a] = (int)floor(pos[3 * i + a] / cs[a]);
+                if (b[a] < 0) b[a] = 0;
+                if (b[a] >= nb[a]) b[a] = nb[a] - 1;
+            }
+            cell[i] = b[0] + (int64_t)nb[0] * (b[1] + (int64_t)nb[1] * b[2]);
+            cnt[cell[i]]++;
+        }
+        start[0] = 0;
+        for (int64_t c = 0; c < ncell; ++c) start[c + 1] = start[c] + cnt[c];
+        memset(cnt, 0, sizeof(int64_t) * (size_t)ncell);
+        for (int64_t i = 0; i < n; ++i) order[start[cell[i]] + cnt[cell[i]]++] = i;
+        double maxov = 0.0;
+        for (int64_t c = 0; c < ncell; ++c) {
+            const int cx = (int)(c % nb[0]), cy = (int)((c / nb[0]) % nb[1]), cz = (int)(c / ((int64_t)nb[0] * nb[1]));
+            for (int64_t t = start[c]; t < start[c + 1]; ++t) {
+                const int64_t i = order[t];
+                for (int dz = -1; dz <= 1; ++dz)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            int q[3] = {cx + dx, cy + dy, cz + dz}, ok = 1;
+                            for (int a = 0; a < 3; ++a) {
+                                if (q[a] < 0 || q[a] >= nb[a]) {
+                                    if (per[a]) q[a] = (q[a] + nb[a]) % nb[a];
+                                    else ok = 0;
+                                }
+                            }
+                            if (!ok) continue;
+                            /* with fewer than 3 cells on an axis a neighbour cell repeats;
+                             * visit each distinct cell once */
+                            int dup = 0;
+                            for (int a = 0; a < 3 && !dup; ++a) {
+                                const int d = a == 0 ? dx : (a == 1 ? dy : dz);
+                                if (nb[a] == 1 && d != 0) dup = 1;
+                                if (nb[a] == 2 && d == 1) dup = 1;
+                            }
+                            if (dup) continue;
+                            const int64_t c2 = q[0] + (int64_t)nb[0] * (q[1] + (int64_t)nb[1] * q[2]);
+                            for (int64_t u = start[c2]; u < start[c2 + 1]; ++u) {
+                                const int64_t j = order[u];
+                                if (j <= i) continue;
+                                double d[3], d2 = 0.0;
+                                for (int a = 0; a < 3; ++a) {
+                                    d[a] = pos[3 * j + a] - pos[3 * i + a];
+                                    if (per[a]) d[a] -= box[a] * nearbyint(d[a] / box[a]);
+                                    d2 += d[a] * d[a];
+                                }
+                                const double s = r[i] + r[j];
+                                if (d2 >= s * s) continue;
+                                const double dist = sqrt(d2);
+                                const double ov = s - dist;
+                                if (ov > maxov) maxov = ov;
+                                const double push = 0.5 * ov + 0.5 * tol;
+                                double nrm[3];
+                                for (int a = 0; a < 3; ++a) nrm[a] = dist > 1e-12 ? d[a] / dist : (a == 0 ? 1.0 : 0.0);
+                                for (int a = 0; a < 3; ++a) {
+                                    pos[3 * i + a] -= push * nrm[a];
+                                    pos[3 * j + a] += push * nrm[a];
+                                }
+                            }
+                        }
+            }
+        }
+        for (int64_t i = 0; i < n; ++i)
+            for (int a = 0; a < 3; ++a) {
+                double *x = &pos[3 * i + a];
+                if (per[a]) *x = wrapd(*x, box[a]);
+                else {
+                    if (*x < r[i]) *x = r[i];
+                    if (*x > box[a] - r[i]) *x = box[a] - r[i];
+                }
+            }
+        if (maxov < tol) {
+            result = sweep + 1;
+            break;
+        }
+    }
+    free(start);
+    free(cnt);
+    free(order);
+    free(cell);
+    return result;
+}

@@ -57,6 +57,18 @@ class lbdem_state_view(C.Structure):
                 ("rho_p", C.c_void_p)]
 
 
+class lbdem_request(C.Structure):
+    _fields_ = [("params", lbdem_params), ("np", C.c_int64), ("x", C.c_void_p), ("u", C.c_void_p),
+                ("omega", C.c_void_p), ("d", C.c_void_p), ("rho_p", C.c_void_p),
+                ("steps", C.c_int64), ("avg_from", C.c_int64)]
+
+
+class lbdem_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("steps_done", C.c_int64), ("u_ps", C.c_double),
+                ("mean_eps_f", C.c_double), ("mom", C.c_double * 3), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
 _lib = None
 
 
@@ -88,6 +100,21 @@ def lib():
             "lbdem_save_state": (st, [H, C.c_void_p, C.POINTER(C.c_size_t)]),
             "lbdem_load_state": (st, [H, C.c_void_p, C.c_size_t]),
             "lbdem_set_timing": (st, [H, C.c_int]),
+            "lbdem_autotune": (st, [H, C.POINTER(C.c_int32)]),
+            "lbdem_batch_create": (st, [C.c_int32, C.POINTER(lbdem_params), C.c_void_p, C.POINTER(H)]),
+            "lbdem_batch_domain": (st, [H, C.c_int32, C.POINTER(H)]),
+            "lbdem_batch_size": (C.c_int32, [H]),
+            "lbdem_batch_autotune": (st, [H]),
+            "lbdem_batch_step": (st, [H, C.c_int64]),
+            "lbdem_batch_sync": (st, [H]),
+            "lbdem_batch_destroy": (st, [H]),
+            "lbdem_server_last_error": (C.c_char_p, []),
+            "lbdem_server_create": (st, [C.c_size_t, C.c_int32, C.c_int32, C.POINTER(H)]),
+            "lbdem_server_submit": (st, [H, C.POINTER(lbdem_request), C.POINTER(C.c_uint64)]),
+            "lbdem_server_poll": (st, [H, C.c_uint64, C.POINTER(lbdem_result)]),
+            "lbdem_server_cancel": (st, [H, C.c_uint64]),
+            "lbdem_server_stats": (st, [H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
+            "lbdem_server_destroy": (st, [H]),
             "lbdem_kernel_time": (st, [H, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         }
         for name, (res, args) in sig.items():
@@ -130,18 +157,22 @@ def params_from(prm) -> lbdem_params:
 class Domain:
     """One domain of the C library (lbdem_create ... lbdem_destroy)."""
 
-    def __init__(self, prm, stream=None):
+    def __init__(self, prm, stream=None, handle=None):
         self.prm = prm
         self.P = params_from(prm)
-        self.h = C.c_void_p()
-        s = None if stream is None else C.c_void_p(int(stream))
-        _check(None, lib().lbdem_create(C.byref(self.P), s, C.byref(self.h)))
+        self.owned = handle is None
+        if handle is None:
+            self.h = C.c_void_p()
+            s = None if stream is None else C.c_void_p(int(stream))
+            _check(None, lib().lbdem_create(C.byref(self.P), s, C.byref(self.h)))
+        else:
+            self.h = handle
         self.nc = int(lib().lbdem_num_cells(self.h))
 
     def close(self):
-        if self.h:
+        if self.h and self.owned:
             lib().lbdem_destroy(self.h)
-            self.h = C.c_void_p()
+        self.h = C.c_void_p()
 
     def __del__(self):
         try:
@@ -242,11 +273,136 @@ class Domain:
     def lbdem_set_timing(self, on: bool):
         _check(self.h, lib().lbdem_set_timing(self.h, 1 if on else 0))
 
+    def lbdem_autotune(self):
+        v = C.c_int32(-1)
+        _check(self.h, lib().lbdem_autotune(self.h, C.byref(v)))
+        return v.value
+
     def lbdem_kernel_time(self, cls):
         ms = C.c_double(0.0); n = C.c_int64(0)
         c = KCLASS[cls] if isinstance(cls, str) else int(cls)
         _check(self.h, lib().lbdem_kernel_time(self.h, c, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+
+class Batch:
+    """Many independent domains advanced by one graph (lbdem_batch_*)."""
+
+    def __init__(self, prms, stream=None):
+        arr = (lbdem_params * len(prms))(*[params_from(p) for p in prms])
+        self.h = C.c_void_p()
+        s = None if stream is None else C.c_void_p(int(stream))
+        _check(None, lib().lbdem_batch_create(len(prms), arr, s, C.byref(self.h)))
+        self.domains = []
+        for i, p in enumerate(prms):
+            dh = C.c_void_p()
+            _check(None, lib().lbdem_batch_domain(self.h, i, C.byref(dh)))
+            self.domains.append(Domain(p, handle=dh))
+
+    def lbdem_batch_autotune(self):
+        _check(None, lib().lbdem_batch_autotune(self.h))
+        out = []
+        for d in self.domains:
+            v = C.c_int32(-1)
+            _check(d.h, lib().lbdem_autotune(d.h, C.byref(v)))
+            out.append(v.value)
+        return out
+
+    def lbdem_batch_step(self, nsteps=1):
+        _check(None, lib().lbdem_batch_step(self.h, int(nsteps)))
+
+    def lbdem_batch_sync(self):
+        _check(None, lib().lbdem_batch_sync(self.h))
+
+    def step(self, nsteps=1):
+        self.lbdem_batch_step(nsteps)
+        self.lbdem_batch_sync()
+
+    def close(self):
+        if self.h:
+            for d in self.domains:
+                d.h = C.c_void_p()
+            lib().lbdem_batch_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _scheck(status):
+    if status != OK:
+        msg = lib().lbdem_server_last_error()
+        raise LbdemError(status, msg.decode() if msg else "")
+
+
+class Server:
+    """Request loop for settling solves (lbdem_server_*)."""
+
+    def __init__(self, hbm_budget, max_slots=64, chunk_steps=20):
+        self.h = C.c_void_p()
+        _scheck(lib().lbdem_server_create(int(hbm_budget), int(max_slots), int(chunk_steps), C.byref(self.h)))
+
+    def lbdem_server_submit(self, prm, particles, steps, avg_from=0):
+        P = particles
+        arrs = [np.ascontiguousarray(v, np.float64) for v in (P.x, P.u, P.w, P.d, P.rho_p)]
+        R = lbdem_request(params_from(prm), len(arrs[3]), *[_ptr(a).value for a in arrs], int(steps), int(avg_from))
+        t = C.c_uint64(0)
+        _scheck(lib().lbdem_server_submit(self.h, C.byref(R), C.byref(t)))
+        return t.value
+
+    def lbdem_server_poll(self, ticket):
+        R = lbdem_result()
+        st = lib().lbdem_server_poll(self.h, int(ticket), C.byref(R))
+        if st == E_BUSY:
+            return None
+        _scheck(st)
+        return dict(status=R.status, steps_done=R.steps_done, u_ps=R.u_ps, mean_eps_f=R.mean_eps_f,
+                    mom=np.array(R.mom[:]), t_submit=R.t_submit, t_admit=R.t_admit, t_done=R.t_done)
+
+    def lbdem_server_cancel(self, ticket):
+        return lib().lbdem_server_cancel(self.h, int(ticket))
+
+    def lbdem_server_stats(self):
+        q = C.c_int64(0); a = C.c_int64(0); b = C.c_size_t(0)
+        _scheck(lib().lbdem_server_stats(self.h, C.byref(q), C.byref(a), C.byref(b)))
+        return dict(queued=q.value, active=a.value, bytes=b.value)
+
+    def wait(self, ticket, timeout=600.0, poll_s=0.002):
+        import time
+        t0 = time.time()
+        while True:
+            r = self.lbdem_server_poll(ticket)
+            if r is not None:
+                return r
+            if time.time() - t0 > timeout:
+                raise TimeoutError(f"request {ticket} not done after {timeout} s")
+            time.sleep(poll_s)
+
+    def close(self):
+        if self.h:
+            lib().lbdem_server_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def exported_symbols():
