@@ -1,7 +1,9 @@
 #!/usr/bin/env python3
 """Throughput of the coupled LBM-DEM time step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dilute|small|dense]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dilute|dilute64|small]
+    python bench.py --mode batch [--domains 256] [--steps K]
+    python bench.py --mode serve [--requests R] [--rates 10,100]
 
 A step is one full coupled time step (Alg. 1 of the paper): moments, Du_f/Dt
 and grad P, n_int interaction subcycles (added mass, drag, pressure and
@@ -29,6 +31,39 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "MLUPS & % HBM roofline per coupled step; batched solves/s + p50/p99 latency"
+
+
+def _gen_batch_domain(args):
+    from paper_1711_00336_amd import inputs as I
+    seed, i, precision = args
+    return I.case_batch_domain(seed, i, precision=precision)
+
+
+def _gen_request(args):
+    from paper_1711_00336_amd import inputs as I
+    seed, i = args
+    edge, eps, d, rr, steps = I.serving_request_draw(seed, i)
+    c = I.case_settling(seed * 1000003 + i, edge, eps, d, rr, precision="fp32dev", tau=I.SWEEP_TAU)
+    return c, steps
+
+
+def _pool_map(fn, items, what):
+    """Generate inputs on the host in a process pool (CPU share: at most 16)."""
+    import concurrent.futures as cf
+    workers = max(1, min(16, os.cpu_count() or 1, len(items)))
+    out = [None] * len(items)
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(workers) as ex:
+        futs = {ex.submit(fn, it): k for k, it in enumerate(items)}
+        done = 0
+        for f in cf.as_completed(futs):
+            out[futs[f]] = f.result()
+            done += 1
+            if done % max(1, len(items) // 8) == 0 or done == len(items):
+                print(f"[bench] generated {done}/{len(items)} {what} ({time.perf_counter() - t0:.0f} s)",
+                      file=sys.stderr, flush=True)
+    return out
 
 
 def workload(name, seed):
@@ -42,14 +77,108 @@ def workload(name, seed):
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_bytes(case):
-    """Algorithmic HBM bytes per launch of each timed kernel class.
+def mean_list_length(case, vskin=0.4):
+    """Mean Verlet-list length of the initial packing: neighbours within
+    (d_i + d_j)/2 + h_c + skin (the list reach of the DEM kernels)."""
+    from paper_1711_00336_amd import inputs as I
+    P, p = case.particles, case.params
+    if P.n < 2:
+        return 0.0
+    h = max(p.h_c, 0.0) if p.use_lub else 0.0
+    cut = lambda i, j: 0.5 * (P.d[i] + P.d[j]) + h + vskin
+    I_, _J, _dv = I._neighbour_pairs(P.x, list(p.n), list(p.periodic), float(P.d.max()) + h + vskin, cut)
+    return 2.0 * len(I_) / P.n
 
-    stream_collide: per cell 19 PDF reads + 19 PDF writes + solid fraction +
-    3 force components, in the storage precision."""
+
+def kernel_bytes(case, nlist):
+    """Algorithmic HBM bytes per launch of each timed kernel class: what the
+    operation must read and write once (re-reads of neighbour cells or
+    particles, which a cache can serve, are not counted). rs is the cell
+    storage size (4 B FP32-deviation, 8 B FP64); particle state is FP64.
+
+      stream_collide  per cell 19 PDF reads + 19 writes + eps_p + f_acc(3)  42 rs
+      moments         per cell 19 PDFs + eps_p read, rho, j, u_f written    27 rs
+      cellfields      per cell u_f, rho, u_prev read; Du/Dt, grad P,
+                      u_prev, f_acc written                                 19 rs
+      part_am         per particle stencil (9 weights, 3 ints), a, d, rho
+                      read, F_am written; per cell Du/Dt read        140 B + 3 rs
+      part_drag       per particle stencil, u, d, rho, F_am, id read,
+                      F_d, F_const written; per cell u_f, grad P, eps_p
+                      read                                           200 B + 7 rs
+      gather_am       per cell eps_p, rho, j read, f_am, u_f written;
+                      per particle 9 weights + F_am                   11 rs + 96 B
+      gather_fd       per cell eps_p, f_am, f_acc read, f_acc written;
+                      per particle 9 weights + F_d                    10 rs + 96 B
+      gather_eps      per cell rho, j read, eps_p, f_am, u_f written;
+                      per particle 9 weights + d + F_am              11 rs + 104 B
+      dem_force       per particle x, u, omega, d, rho, id, list length,
+                      L list entries read, F, T written          140 B + 4 L B
+      integrate       per particle x, u, omega, F_const, F, T, d, rho,
+                      x_start read; x, u, omega written                 256 B
+    """
     rs = 4 if case.params.precision == "fp32dev" else 8
-    nc = case.params.n[0] * case.params.n[1] * case.params.n[2]
-    return {"stream_collide": nc * (19 + 19 + 1 + 3) * rs}
+    nc = int(np.prod(case.params.n))
+    n = int(case.particles.n)
+    return {"stream_collide": nc * 42 * rs, "moments": nc * 27 * rs, "cellfields": nc * 19 * rs,
+            "part_am": n * 140 + nc * 3 * rs, "part_drag": n * 200 + nc * 7 * rs,
+            "gather_am": nc * 11 * rs + n * 96, "gather_fd": nc * 10 * rs + n * 96,
+            "gather_eps": nc * 11 * rs + n * 104,
+            "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * 256}
+
+
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SRC = os.path.join(ROOT, "paper_1711_00336_amd", "csrc", "lbdem_kernels.hip")
+
+
+def measured_traffic(kernel_class, workload_name):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel and workload (FETCH_SIZE + WRITE_SIZE, each scaled by the
+    same counter on a plain device copy of known size), or None when there is
+    none or the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(PROFILES, f"traffic_{kernel_class}_{workload_name}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if vals.get("kernel_source_sha256") != src:
+        return None
+    try:
+        return int(float(vals["hbm_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def k10_roofline(lbdem, stream, steps=10, warmup=3):
+    """Fused stream-collide alone on the dense-suspension grid (256 x 256 x 512
+    cells, walls in z, FP32 deviations): 2 x 2.55 GB of PDFs per step, far
+    beyond the last-level cache, so its time is HBM time. No particles: the
+    kernel does the same work per cell with eps_f = 1 and f_acc = 0."""
+    from paper_1711_00336_amd import inputs as I
+    prm = I.Params(n=(256, 256, 512), periodic=(1, 1, 0), tau=0.7, precision="fp32dev")
+    dom = lbdem.Domain(prm, stream=stream.cuda_stream)
+    try:
+        dom.lbdem_step(warmup)
+        dom.lbdem_sync()
+        dom.lbdem_set_timing(True)
+        dom.lbdem_step(steps)
+        dom.lbdem_sync()
+        ms, n = dom.lbdem_kernel_time("stream_collide")
+        dom.lbdem_set_timing(False)
+    finally:
+        dom.close()
+    nc = 256 * 256 * 512
+    byts = nc * 42 * 4
+    avg = ms / n
+    ach = byts / (avg * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "stream_collide", "workload": "fluid-256x256x512-fp32dev",
+            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("stream_collide", "fluid-256x256x512"),
+            "bytes_per_launch": byts, "avg_launch_ms": round(avg, 5)}
 
 
 def cpu_baseline(case, budget_s=20.0):
@@ -85,20 +214,208 @@ def cpu_baseline(case, budget_s=20.0):
             "sample": f"{desc}, FP64 oracle, {k} coupled steps in {dt:.1f} s"}
 
 
+def bench_batch(args):
+    """Batched sweep: many uneven periodic settling domains (edges log-uniform
+    16..96, solid fraction 0.01..0.5, d 0.6..1.0, density ratio 1.5..4)
+    advanced together by lbdem_batch_step, in FP32-deviation and FP64, beside
+    the plain per-domain FP64 path (each domain stepped alone, one after the
+    other). A solve is 1000 coupled steps of one domain."""
+    import torch
+    from paper_1711_00336_amd import lbdem
+    nd, K, W = args.domains, args.steps, args.warmup
+    cases = _pool_map(_gen_batch_domain, [(args.seed, i, "fp32dev") for i in range(nd)], "domains")
+    cells = int(sum(int(np.prod(c.params.n)) for c in cases))
+    parts = int(sum(c.particles.n for c in cases))
+    print(f"[bench] batch of {nd} domains: {cells} cells, {parts} particles", file=sys.stderr, flush=True)
+    torch.cuda.init()
+    runs = {}
+    for prec in ("fp32dev", "fp64"):
+        b = lbdem.Batch([c.params.copy(precision=prec) for c in cases])
+        for d, c in zip(b.domains, cases):
+            d.add(c.particles)
+        variants = b.lbdem_batch_autotune()
+        b.lbdem_batch_step(W)
+        b.lbdem_batch_sync()
+        t0 = time.perf_counter()
+        b.lbdem_batch_step(K)
+        b.lbdem_batch_sync()
+        dt = time.perf_counter() - t0
+        ups = np.array([d.lbdem_diagnostics()["u_ps"] for d in b.domains])
+        b.close()
+        runs[prec] = dict(dt=dt, ups=ups, variants=variants)
+        print(f"[bench] batch {prec}: {K} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+    # plain path: every domain alone, FP64, one after the other
+    dt_plain = 0.0
+    ups_plain = []
+    for c in cases:
+        dom = lbdem.Domain(c.params.copy(precision="fp64"))
+        dom.add(c.particles)
+        dom.lbdem_step(W)
+        dom.lbdem_sync()
+        t0 = time.perf_counter()
+        dom.lbdem_step(K)
+        dom.lbdem_sync()
+        dt_plain += time.perf_counter() - t0
+        ups_plain.append(dom.lbdem_diagnostics()["u_ps"])
+        dom.close()
+    ups_plain = np.array(ups_plain)
+    print(f"[bench] plain per-domain fp64: {K} steps of every domain in {dt_plain:.3f} s", file=sys.stderr, flush=True)
+
+    def solves(dt):
+        return nd / (dt / K * 1000.0)
+
+    rel = np.abs(runs["fp32dev"]["ups"] - ups_plain) / np.maximum(np.abs(ups_plain), 1e-30)
+    out = {
+        "metric": METRIC, "mode": "batch",
+        "value": round(solves(runs["fp32dev"]["dt"]), 4), "unit": "solves/s (1000-step settling solves)",
+        "n_gpus": 1, "steps": K, "warmup": W, "higher_is_better": True, "data": "synthetic",
+        "config": {"workload": f"batched-sweep-{nd}-domains", "domains": nd, "cells": cells, "particles": parts,
+                   "tau": cases[0].params.tau, "n_int": cases[0].params.n_int},
+        "batch_fp32dev": {"ms_per_step": round(runs["fp32dev"]["dt"] / K * 1e3, 3),
+                          "mlups": round(cells * K / runs["fp32dev"]["dt"] / 1e6, 2),
+                          "solves_per_s": round(solves(runs["fp32dev"]["dt"]), 4)},
+        "batch_fp64": {"ms_per_step": round(runs["fp64"]["dt"] / K * 1e3, 3),
+                       "mlups": round(cells * K / runs["fp64"]["dt"] / 1e6, 2),
+                       "solves_per_s": round(solves(runs["fp64"]["dt"]), 4)},
+        "plain_fp64": {"ms_per_step": round(dt_plain / K * 1e3, 3),
+                       "mlups": round(cells * K / dt_plain / 1e6, 2),
+                       "solves_per_s": round(solves(dt_plain), 4)},
+        "speedup_vs_plain_fp64": round(dt_plain / runs["fp32dev"]["dt"], 3),
+        "u_ps_fp64_batch_equals_plain": bool(np.array_equal(runs["fp64"]["ups"], ups_plain)),
+        "u_ps_fp32_vs_plain_fp64_max_rel": float(rel.max()),
+        "tile_variants": {str(v): int(sum(1 for x in runs["fp32dev"]["variants"] if x == v))
+                          for v in sorted(set(runs["fp32dev"]["variants"]))},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Serving: Poisson arrivals of settling requests (edges log-uniform
+    24..160, solid fraction 0.01..0.5, 200..5000 steps, FP32-deviation) into
+    the request loop with an HBM budget of 0.9 x free HBM. Latency is arrival
+    to result, queueing included. The plain FP64 path at the same offered
+    load is a first-come-first-served queue, one request at a time, whose
+    service times are measured per request on a sample of its steps and
+    scaled to its step count."""
+    import torch
+    from paper_1711_00336_amd import inputs as I
+    from paper_1711_00336_amd import lbdem
+    rates = [float(x) for x in args.rates.split(",")]
+    R = args.requests
+    torch.cuda.init()
+    lines = []
+    for rate in rates:
+        seed = args.seed * 7 + int(rate)
+        gen = _pool_map(_gen_request, [(seed, i) for i in range(R)], f"requests (rate {rate:g}/s)")
+        arrivals = I.poisson_arrivals(seed, rate, R)
+        free, _total = torch.cuda.mem_get_info()
+        budget = int(0.9 * free)
+        srv = lbdem.Server(budget, max_slots=args.slots, chunk_steps=args.chunk)
+        trace = []
+        tickets = []
+        t0 = time.perf_counter()
+        k = 0
+        while k < R:
+            now = time.perf_counter() - t0
+            if now >= arrivals[k]:
+                c, steps = gen[k]
+                tickets.append(srv.lbdem_server_submit(c.params, c.particles, steps, avg_from=steps // 2))
+                k += 1
+                continue
+            trace.append((now, srv.lbdem_server_stats()["active"]))
+            time.sleep(min(0.01, arrivals[k] - now))
+        results = []
+        last = time.perf_counter()
+        for t in tickets:
+            while True:
+                r = srv.lbdem_server_poll(t)
+                if r is not None:
+                    break
+                if time.perf_counter() - last > 5.0:
+                    st = srv.lbdem_server_stats()
+                    print(f"[bench] serving rate {rate:g}: {len(results)}/{R} done, active {st['active']}, "
+                          f"queued {st['queued']}", file=sys.stderr, flush=True)
+                    last = time.perf_counter()
+                trace.append((time.perf_counter() - t0, srv.lbdem_server_stats()["active"]))
+                time.sleep(0.01)
+            results.append(r)
+        srv.close()
+        bad = [r for r in results if r["status"] != 0]
+        lat = np.array([r["t_done"] - r["t_submit"] for r in results])
+        span = max(r["t_done"] for r in results) - min(r["t_submit"] for r in results)
+        cells = np.array([int(np.prod(c.params.n)) for c, _ in gen])
+        steps = np.array([s for _, s in gen])
+        # plain FP64 path: measured service times, FCFS single queue
+        svc = []
+        for c, st in gen:
+            dom = lbdem.Domain(c.params.copy(precision="fp64"))
+            dom.add(c.particles)
+            dom.lbdem_step(2)
+            dom.lbdem_sync()
+            ks = min(st, args.plain_sample)
+            ta = time.perf_counter()
+            dom.lbdem_step(ks)
+            dom.lbdem_sync()
+            svc.append((time.perf_counter() - ta) / ks * st)
+            dom.close()
+        fin = 0.0
+        lat_plain = []
+        for a, s in zip(arrivals, svc):
+            fin = max(fin, a) + s
+            lat_plain.append(fin - a)
+        lat_plain = np.array(lat_plain)
+        line = {
+            "metric": METRIC, "mode": "serve", "rate_per_s": rate, "requests": R, "failed": len(bad),
+            "value": round(R / span, 4), "unit": "solves/s", "higher_is_better": True, "n_gpus": 1,
+            "data": "synthetic",
+            "config": {"workload": "settling-requests-edge24-160", "hbm_budget_gb": round(budget / 1e9, 1),
+                       "slots": args.slots, "chunk_steps": args.chunk,
+                       "mean_cells": int(cells.mean()), "mean_steps": float(steps.mean())},
+            "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
+            "cell_updates_per_s_mlups": round(float((cells * steps).sum()) / span / 1e6, 2),
+            "max_concurrency": int(max(a for _, a in trace)) if trace else 0,
+            "mean_concurrency": round(float(np.mean([a for _, a in trace])), 2) if trace else 0.0,
+            "plain_fp64_fcfs": {"solves_per_s": round(R / (fin - arrivals[0]), 4),
+                                "p50_s": round(float(np.percentile(lat_plain, 50)), 3),
+                                "p99_s": round(float(np.percentile(lat_plain, 99)), 3),
+                                "service_time_sample_steps": args.plain_sample},
+        }
+        print(json.dumps(line), flush=True)
+        lines.append(line)
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="dilute")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--mode", choices=("step", "batch", "serve"), default="step")
+    ap.add_argument("--domains", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=16)
+    ap.add_argument("--rates", default="10,1000")
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--chunk", type=int, default=50)
+    ap.add_argument("--plain-sample", type=int, default=100)
+    ap.add_argument("--no-k10", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0)
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = {"step": 200, "batch": 20, "serve": 0}[args.mode]
+    if args.warmup is None:
+        args.warmup = {"step": 20, "batch": 3, "serve": 0}[args.mode]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the spatial decomposition across GPUs is a design, not part of this build)", file=sys.stderr)
         sys.exit(2)
+    if args.mode == "batch":
+        return bench_batch(args)
+    if args.mode == "serve":
+        return bench_serve(args)
 
     import torch
     from paper_1711_00336_amd import lbdem
@@ -125,7 +442,7 @@ def main():
     print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
 
     # per-kernel-class device time (HIP events on the library's stream)
-    ksteps = max(5, min(args.steps, 50))
+    ksteps = max(5, min(args.steps, 20))
     dom.lbdem_set_timing(True)
     dom.lbdem_step(ksteps)
     dom.lbdem_sync()
@@ -138,13 +455,32 @@ def main():
     diag = dom.lbdem_diagnostics()
     dom.close()
 
-    kb = kernel_bytes(case)
-    sc = times["stream_collide"]
-    achieved = kb["stream_collide"] / (sc["avg_launch_ms"] * 1e-3) / 1e9 if sc["avg_launch_ms"] > 0 else 0.0
-    roofline = {"bound": "hbm", "kernel": "stream_collide", "achieved": round(achieved, 1),
+    nlist = mean_list_length(case)
+    kb = kernel_bytes(case, nlist)
+    dom_cls = max((k for k in kb if times[k]["launches_per_step"] > 0), key=lambda k: times[k]["ms_per_step"])
+    kt = times[dom_cls]
+    achieved = kb[dom_cls] / (kt["avg_launch_ms"] * 1e-3) / 1e9 if kt["avg_launch_ms"] > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": dom_cls, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": kb["stream_collide"],
-                "avg_launch_ms": round(sc["avg_launch_ms"], 5)}
+                "traffic": measured_traffic(dom_cls, args.workload), "bytes_per_launch": kb[dom_cls],
+                "avg_launch_ms": round(kt["avg_launch_ms"], 5), "share_of_step": round(kt["ms_per_step"] / sum(
+                    v["ms_per_step"] for v in times.values()), 4)}
+    if dom_cls == "dem_force":
+        roofline["mean_list_length"] = round(nlist, 2)
+    roof_k10 = None
+    if not args.no_k10:
+        print("[bench] stream-collide alone on the 256x256x512 grid", file=sys.stderr, flush=True)
+        roof_k10 = k10_roofline(lbdem, stream)
+    if args.calib_copy_mib > 0:
+        # a plain device copy of known size, for scaling the HBM byte counters
+        nb = args.calib_copy_mib << 20
+        src_t = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        for _ in range(5):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copies: 5 x {nb} bytes read and written", file=sys.stderr, flush=True)
+        del src_t, dst_t
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -153,7 +489,7 @@ def main():
 
     ms_per_step = dt / args.steps * 1e3
     out = {
-        "metric": "MLUPS per coupled LBM-DEM step (whole job)",
+        "metric": METRIC,
         "value": round(nc * args.steps / dt / 1e6, 2),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -170,6 +506,7 @@ def main():
                    "pdf_storage": "f32 deviation" if case.params.precision == "fp32dev" else "f64 deviation",
                    "particle_integration": "f64", "tau": case.params.tau},
         "roofline": roofline,
+        "roofline_stream_collide": roof_k10,
         "cpu_baseline": cpu,
         "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in times.items()},
         "u_ps": diag["u_ps"],

@@ -185,17 +185,32 @@ lbdem_status lbdem_set_state(lbdem_domain_t h, const lbdem_state_view *v);
 lbdem_status lbdem_save_state(lbdem_domain_t h, void *blob, size_t *size);
 lbdem_status lbdem_load_state(lbdem_domain_t h, const void *blob, size_t size);
 
-/* Launch-configuration query for benchmarks: average device time in ms of
- * the named kernel class over the last lbdem_step call when timing is on
- * (lbdem_set_timing). Classes: 0 stream-collide, 1 moments, 2 cell fields,
- * 3 particle passes, 4 gathers, 5 DEM, 6 binning. */
+/* Per-kernel device time for benchmarks. While timing is on
+ * (lbdem_set_timing(h, 1); steps then launch kernel by kernel with HIP
+ * events on the domain's stream instead of replaying graphs),
+ * lbdem_kernel_time returns the total device time in ms and the number of
+ * launches of one kernel class since timing was switched on. Classes:
+ * 0 stream-collide, 1 moments, 2 cell fields (Du/Dt, grad P), 3 added-mass
+ * particle pass, 4 drag/pressure particle pass, 5 added-mass spreading,
+ * 6 drag spreading and f_acc, 7 volume fraction (+ next added-mass
+ * spreading), 8 Verlet list build, 9 DEM contact/lubrication forces,
+ * 10 DEM integration, 11 particle binning and reordering.
+ * E_INVALID for a class outside 0..11. */
 lbdem_status lbdem_set_timing(lbdem_domain_t h, int on);
 lbdem_status lbdem_kernel_time(lbdem_domain_t h, int cls, double *ms_total, int64_t *launches);
 
 /* Pick launch shapes for this domain by timing them on its current state
- * (gather tile shape; results are bit-identical across choices). Optional
- * out: the chosen tile variant (0 16x4x4, 1 8x4x4, 2 8x8x4). */
+ * (the gather variant; results are bit-identical across choices, since every
+ * variant sums a cell's particles in the same order). Optional out: the
+ * chosen variant, as for lbdem_set_gather_variant. */
 lbdem_status lbdem_autotune(lbdem_domain_t h, int32_t *gather_variant);
+
+/* Fix the gather variant (the launch shape of the particle-to-cell sums of
+ * the volume fraction and the spread forces): -1 automatic by particle
+ * density (the default), 0 LDS tiles of 16x4x8 cells, 1 LDS tiles of
+ * 16x4x4, 2 LDS tiles of 8x4x4, 3 one thread per cell reading the particle
+ * bins from global memory. E_INVALID for other values. */
+lbdem_status lbdem_set_gather_variant(lbdem_domain_t h, int32_t variant);
 
 /* ---- Batching: many independent domains (e.g. a parameter sweep of the
  * settling problem of Sec. 4.1) advanced together. One batch step replays a

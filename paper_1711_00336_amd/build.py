@@ -21,8 +21,11 @@ ROOT = os.path.dirname(HERE)
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-# Packed FP32 VALU forms are disabled for all device code.
-DEVICE_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+# Packed FP32 VALU forms are disabled for all device code. Multiply-adds are
+# fused only within one source expression (-ffp-contract=on), so a kernel
+# rounds the same way whatever the surrounding code it is inlined into: the
+# launch variants of one operation then agree bit for bit.
+DEVICE_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=on",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                 "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function"]
 HOST_FLAGS = ["-O2", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",

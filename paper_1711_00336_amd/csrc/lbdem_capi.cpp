@@ -98,8 +98,8 @@ struct lbdem_domain {
     };
     std::vector<Ev> ev_pool;
     size_t ev_used = 0;
-    double cls_ms[8] = {0};
-    int64_t cls_n[8] = {0};
+    double cls_ms[kTimingClasses] = {0};
+    int64_t cls_n[kTimingClasses] = {0};
 
     size_t rsize() const { return prec == LBDEM_FP64 ? sizeof(double) : sizeof(float); }
 
@@ -511,22 +511,22 @@ void enqueue_step(lbdem_domain_t h)
     launch_cls(h, 1, [&] { launch_moments<R>(h->desc(), C, s); });
     launch_cls(h, 2, [&] { launch_cellfields<R>(h->desc(), C, s); });
     launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
-    launch_cls(h, 4, [&] { launch_gather_am<R>(h->desc(), C, s); });
+    launch_cls(h, 5, [&] { launch_gather_am<R>(h->desc(), C, s); });
     for (int k = 0; k < nint; ++k) {
         const int last_sub = k == nint - 1;
-        launch_cls(h, 3, [&] { launch_part_drag<R>(h->desc(), C, last_sub, s); });
-        launch_cls(h, 4, [&] { launch_gather_fd<R>(h->desc(), C, s); });
-        launch_cls(h, 5, [&] { launch_nlist(h->desc(), s); });
+        launch_cls(h, 4, [&] { launch_part_drag<R>(h->desc(), C, last_sub, s); });
+        launch_cls(h, 6, [&] { launch_gather_fd<R>(h->desc(), C, s); });
+        launch_cls(h, 8, [&] { launch_nlist(h->desc(), s); });
         for (int sub = 0; sub < h->phys.n_dem; ++sub) {
-            launch_cls(h, 5, [&] { launch_dem_force(h->desc(), s); });
-            launch_cls(h, 5, [&] { launch_integrate(h->desc(), sub == h->phys.n_dem - 1, s); });
+            launch_cls(h, 9, [&] { launch_dem_force(h->desc(), s); });
+            launch_cls(h, 10, [&] { launch_integrate(h->desc(), sub == h->phys.n_dem - 1, s); });
         }
-        launch_cls(h, 6, [&] { sort_particles(h); });
+        launch_cls(h, 11, [&] { sort_particles(h); });
         if (!last_sub) {
             launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
-            launch_cls(h, 4, [&] { launch_gather_eps_am<R>(h->desc(), C, s); });
+            launch_cls(h, 7, [&] { launch_gather_eps_am<R>(h->desc(), C, s); });
         } else {
-            launch_cls(h, 4, [&] { launch_gather_eps<R>(h->desc(), C, s); });
+            launch_cls(h, 7, [&] { launch_gather_eps<R>(h->desc(), C, s); });
         }
     }
     launch_cls(h, 0, [&] { launch_stream_collide<R>(h->desc(), C, s); });
@@ -1092,6 +1092,18 @@ lbdem_status lbdem_autotune(lbdem_domain_t h, int32_t *gather_variant)
     });
 }
 
+lbdem_status lbdem_set_gather_variant(lbdem_domain_t h, int32_t variant)
+{
+    if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
+    if (variant < -1 || variant >= kGatherVariants) return fail(h, LBDEM_E_INVALID, "unknown gather variant");
+    return guarded(h, [&]() -> lbdem_status {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        h->tune.gather = variant;
+        h->drop_graphs();
+        return LBDEM_OK;
+    });
+}
+
 lbdem_status lbdem_set_timing(lbdem_domain_t h, int on)
 {
     if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
@@ -1099,7 +1111,7 @@ lbdem_status lbdem_set_timing(lbdem_domain_t h, int on)
         hip_check(hipStreamSynchronize(h->stream), "sync");
         if (h->timing) harvest_timing(h);
         h->timing = on != 0;
-        for (int c = 0; c < 8; ++c) {
+        for (int c = 0; c < kTimingClasses; ++c) {
             h->cls_ms[c] = 0.0;
             h->cls_n[c] = 0;
         }
@@ -1109,7 +1121,7 @@ lbdem_status lbdem_set_timing(lbdem_domain_t h, int on)
 
 lbdem_status lbdem_kernel_time(lbdem_domain_t h, int cls, double *ms_total, int64_t *launches)
 {
-    if (!h || cls < 0 || cls >= 8) return fail(h, LBDEM_E_INVALID, "bad argument");
+    if (!h || cls < 0 || cls >= kTimingClasses) return fail(h, LBDEM_E_INVALID, "bad argument");
     return guarded(h, [&]() -> lbdem_status {
         hip_check(hipStreamSynchronize(h->stream), "sync");
         if (h->timing) harvest_timing(h);

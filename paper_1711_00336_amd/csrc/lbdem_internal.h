@@ -82,7 +82,7 @@ struct Parts {
 
 // launch choices picked per domain (autotuner); -1 = heuristic default
 struct Tune {
-    int gather;                 // gather tile: 0 16x4x4, 1 8x4x4, 2 8x8x4
+    int gather;                 // -1 by density; 0/1/2 LDS tiles 16x4x8, 16x4x4, 8x4x4; 3 per cell
 };
 
 struct Desc {
@@ -103,6 +103,7 @@ enum : int {
     FLAG_NLIST = 16             // a particle has more than kNbr list neighbours
 };
 
+constexpr int kTimingClasses = 12;  // kernel classes of lbdem_kernel_time
 constexpr int kNbr = 80;        // Verlet list capacity per particle
 
 constexpr int kBlock = 256;
@@ -118,7 +119,7 @@ template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, in
 template <typename R> void launch_gather_fd(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_eps_am(const Desc &D, const Cells<R> &C, hipStream_t s);
-constexpr int kGatherVariants = 3;
+constexpr int kGatherVariants = 4;
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s);
 template <typename R> void launch_to_double(const R *src, double *dst, int64_t n, hipStream_t s);

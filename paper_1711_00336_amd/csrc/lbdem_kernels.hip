@@ -387,12 +387,14 @@ __device__ __forceinline__ void gather_cell(const Desc &D, int i, int j, int k, 
 }
 
 // ---------------------------------------------------------------------------
-// LDS-tiled gather. A workgroup owns a TX x TY x TZ tile of cells. It counts
-// the particles of the tile's halo bins (the tile widened by one cell, wrapped
-// on periodic axes), stages their stencils and values into LDS with coalesced
-// loads (bins are contiguous slot ranges), and then every cell sums the
-// particles of its own 3x3x3 bins from LDS. Tiles whose halo holds more than
-// KMAX particles fall back to the per-cell global gather.
+// LDS-tiled gather. A workgroup owns a TX x TY x (TZ*CZ) tile of cells, each
+// thread CZ consecutive cells along z. It counts the particles of the tile's
+// halo bins (the tile widened by one cell, wrapped on periodic axes), stages
+// their stencils and values into LDS (a bin's particles are one contiguous
+// slot range, staged by the thread that owns the bin), and then every cell
+// sums the particles of its own 3x3x3 bins from LDS, in the order
+// (dz, dy, dx, slot) whatever the tile shape. Tiles whose halo holds more
+// than KMAX particles fall back to the per-cell global gather.
 //   MODE_AM : fam  = -sum_p D F_am                    (Eq. forces_pf, added mass)
 //   MODE_FD : facc += (eps_f f_b + fam - sum_p D F_d) / n_int   (mean f_ext)
 //   MODE_EPS: epsp = sum_p D V_p                      (Eq. fluid_volume_fraction)
@@ -462,15 +464,16 @@ __device__ __forceinline__ void gather_store(const Desc &D, const Cells<R> &C, i
     }
 }
 
-template <typename R, int MODE, int TX, int TY, int TZ, int KMAX>
+template <typename R, int MODE, int TX, int TY, int TZ, int CZ, int KMAX>
 __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
 {
-    constexpr int NT = TX * TY * TZ, HX = TX + 2, HY = TY + 2, HZ = TZ + 2, NHB = HX * HY * HZ;
+    constexpr int NT = TX * TY * TZ, HX = TX + 2, HY = TY + 2, HZ = TZ * CZ + 2, NHB = HX * HY * HZ;
     constexpr int NV = GatherNV<MODE>::v;
     constexpr int PER = (NHB + NT - 1) / NT;
+    constexpr int NW = NT / 64;
+    static_assert(NT % 64 == 0, "whole wavefronts");
     __shared__ int hoff[NHB + 1];
-    __shared__ int hsrc[NHB];
-    __shared__ int sscan[NT];
+    __shared__ int wsum[NW];
     __shared__ double sw_l[9][KMAX];
     __shared__ double sv_l[NV][KMAX];
 
@@ -480,16 +483,19 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
                                    gridDim.x * gridDim.y * gridDim.z);
     const int bx = (int)(lin % gridDim.x), by = (int)((lin / gridDim.x) % gridDim.y),
               bz = (int)(lin / (gridDim.x * gridDim.y));
-    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ * CZ;
     // halo bins beyond the last cell of a partial tile (+1) are not needed
-    const int lx = min(x0 + TX, n0) - x0 + 1, ly = min(y0 + TY, n1) - y0 + 1, lz = min(z0 + TZ, n2) - z0 + 1;
+    const int lx = min(x0 + TX, n0) - x0 + 1, ly = min(y0 + TY, n1) - y0 + 1,
+              lz = min(z0 + TZ * CZ, n2) - z0 + 1;
 
-    int cl[PER];
+    // each thread owns PER consecutive halo bins
+    int src[PER], cnt[PER];
     int sum = 0;
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
         const int hb = tid * PER + t;
-        int cnt = 0, src = 0;
+        src[t] = 0;
+        cnt[t] = 0;
         if (hb < NHB) {
             const int hx = hb % HX, hy = (hb / HX) % HY, hz = hb / (HX * HY);
             int g[3] = {x0 - 1 + hx, y0 - 1 + hy, z0 - 1 + hz};
@@ -503,84 +509,101 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
             }
             if (ok) {
                 const int64_t bin = cidx(D.g, g[0], g[1], g[2]);
-                src = D.b.start[bin];
-                cnt = D.b.start[bin + 1] - src;
+                src[t] = D.b.start[bin];
+                cnt[t] = D.b.start[bin + 1] - src[t];
             }
-            hsrc[hb] = src;
         }
-        cl[t] = cnt;
-        sum += cnt;
+        sum += cnt[t];
     }
-    sscan[tid] = sum;
+    // exclusive scan of the per-thread counts: wavefront shuffles, then the
+    // wavefront totals through LDS (one barrier)
+    const int lane = tid & 63, wv = tid >> 6;
+    int incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    for (int off = 1; off < NT; off <<= 1) {
-        const int add = tid >= off ? sscan[tid - off] : 0;
-        __syncthreads();
-        sscan[tid] += add;
-        __syncthreads();
+    int run = incl - sum, K = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const int ws = wsum[w];
+        if (w < wv) run += ws;
+        K += ws;
     }
-    int run = sscan[tid] - sum;
+    // offsets of the halo bins, and the staging of their particles (stencil
+    // weights and values) by the thread that owns the bin
+    const Parts &P = D.pt;
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
         const int hb = tid * PER + t;
         if (hb < NHB) hoff[hb] = run;
-        run += cl[t];
+        for (int q = 0; q < cnt[t]; ++q) {
+            const int kk = run + q;
+            if (kk >= KMAX) break;
+            const int p = src[t] + q;
+#pragma unroll
+            for (int u = 0; u < 9; ++u) sw_l[u][kk] = P.sw[u * P.cap + p];
+            double v[NV];
+            gather_value<MODE>(P, p, v);
+#pragma unroll
+            for (int u = 0; u < NV; ++u) sv_l[u][kk] = v[u];
+        }
+        run += cnt[t];
     }
-    if (tid == NT - 1) hoff[NHB] = sscan[NT - 1];
+    if (tid == NT - 1) hoff[NHB] = K;
     __syncthreads();
-    const int K = hoff[NHB];
 
     const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
-    const int i = x0 + tx, j = y0 + ty, k = z0 + tz;
-    const bool inside = i < n0 && j < n1 && k < n2;
-    const int64_t c = inside ? cidx(D.g, i, j, k) : 0;
-    double s[NV];
+    const int i = x0 + tx, j = y0 + ty, kb = z0 + tz * CZ;
+    if (i >= n0 || j >= n1) return;
+    double s[CZ][NV];
 
     if (K > KMAX) {  // crowded tile: per-cell gather from global memory
-        if (!inside) return;
-        gather_cell<NV>(D, i, j, k, [&](int p, double *v) { gather_value<MODE>(D.pt, p, v); }, s);
-        gather_store<R, MODE>(D, C, c, s);
+#pragma unroll
+        for (int c = 0; c < CZ; ++c) {
+            if (kb + c >= n2) break;
+            gather_cell<NV>(D, i, j, kb + c, [&](int p, double *v) { gather_value<MODE>(D.pt, p, v); }, s[c]);
+            gather_store<R, MODE>(D, C, cidx(D.g, i, j, kb + c), s[c]);
+        }
         return;
     }
 
-    const Parts &P = D.pt;
-    for (int kk = tid; kk < K; kk += NT) {
-        int lo = 0, hi = NHB - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (hoff[mid] <= kk) lo = mid;
-            else hi = mid - 1;
-        }
-        const int p = hsrc[lo] + (kk - hoff[lo]);
 #pragma unroll
-        for (int t = 0; t < 9; ++t) sw_l[t][kk] = P.sw[t * P.cap + p];
-        double v[NV];
-        gather_value<MODE>(P, p, v);
+    for (int c = 0; c < CZ; ++c)
 #pragma unroll
-        for (int t = 0; t < NV; ++t) sv_l[t][kk] = v[t];
-    }
-    __syncthreads();
-    if (!inside) return;
-
-#pragma unroll
-    for (int t = 0; t < NV; ++t) s[t] = 0.0;
-    // The bin of a staged particle fixes its stencil offset relative to this
+        for (int t = 0; t < NV; ++t) s[c][t] = 0.0;
+    // The bin of a staged particle fixes its stencil offset relative to a
     // cell: a particle in bin (i-1+dx, j-1+dy, k-1+dz) sees the cell at offset
     // (1-dx, 1-dy, 1-dz), i.e. weight slots 2-dx, 2-dy, 2-dz of its axes.
+    // Halo row r (z = kb - 1 + r) feeds the thread's cells c with dz = r - c.
 #pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
+    for (int r = 0; r < CZ + 2; ++r)
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy) {
-            const int hb0 = ((tz + dz) * HY + (ty + dy)) * HX + tx;
+            const int hb0 = ((tz * CZ + r) * HY + (ty + dy)) * HX + tx;
             const int k0 = hoff[hb0], k1 = hoff[hb0 + 1], k2 = hoff[hb0 + 2], k3 = hoff[hb0 + 3];
             for (int kk = k0; kk < k3; ++kk) {
                 const int sx = kk < k1 ? 2 : (kk < k2 ? 1 : 0);
-                const double w = sw_l[sx][kk] * sw_l[3 + 2 - dy][kk] * sw_l[6 + 2 - dz][kk];
+                const double wxy = sw_l[sx][kk] * sw_l[3 + 2 - dy][kk];
+                double v[NV];
 #pragma unroll
-                for (int t = 0; t < NV; ++t) s[t] += w * sv_l[t][kk];
+                for (int t = 0; t < NV; ++t) v[t] = sv_l[t][kk];
+#pragma unroll
+                for (int c = 0; c < CZ; ++c) {
+                    const int dz = r - c;
+                    if (dz < 0 || dz > 2) continue;
+                    const double w = wxy * sw_l[6 + 2 - dz][kk];
+#pragma unroll
+                    for (int t = 0; t < NV; ++t) s[c][t] += w * v[t];
+                }
             }
         }
-    gather_store<R, MODE>(D, C, c, s);
+#pragma unroll
+    for (int c = 0; c < CZ; ++c)
+        if (kb + c < n2) gather_store<R, MODE>(D, C, cidx(D.g, i, j, kb + c), s[c]);
 }
 
 // per-cell global gather (thin periodic axes, where a cell's neighbour bins coincide)
@@ -879,14 +902,19 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
     P.xbuild[2 * cap + me] = xi2;
 }
 
-// contact + lubrication force and torque on every particle from its list
+// contact + lubrication force and torque on every particle from its list.
+// The list is walked in chunks of kChunk entries whose indices, slots and
+// particle data are requested together, so their memory latencies overlap;
+// pairs are still summed in list order.
+constexpr int kChunk = 4;
+static_assert(kNbr % kChunk == 0, "list rows hold whole chunks");
+
 __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
 {
     const Parts &P = D.pt;
     const int64_t i = gidx();
     if (i == 0) *P.need = 0;  // lists are current for this subcycle
     if (i >= P.np) return;
-    const int64_t cap = P.cap;
     PV pi;
     load_pv(P, i, pi);
     double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
@@ -894,17 +922,27 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
     const int me = P.id[i];
     const int n = P.nnb[me];
     const int *L = P.nlist + (int64_t)me * kNbr;
-    for (int t = 0; t < n; ++t) {
-        const int j = P.slot_of[L[t]];
-        double dx[3] = {P.x[j] - pi.x[0], P.x[cap + j] - pi.x[1], P.x[2 * cap + j] - pi.x[2]};
-        min_image(D.g, dx);
-        const double reach = pi.r + 0.5 * P.d[j] + gap;
-        if (dot3(dx, dx) >= reach * reach) continue;
-        PV pj;
-        load_pv(P, j, pj);
-        pair_interaction(D.p, pi, pj, dx, F, T);
+    for (int t0 = 0; t0 < n; t0 += kChunk) {
+        const int4 ids = *reinterpret_cast<const int4 *>(L + t0);
+        const int idv[kChunk] = {ids.x, ids.y, ids.z, ids.w};
+        int js[kChunk];
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) js[c] = t0 + c < n ? P.slot_of[idv[c]] : (int)i;
+        PV pj[kChunk];
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) load_pv(P, js[c], pj[c]);
+#pragma unroll
+        for (int c = 0; c < kChunk; ++c) {
+            if (t0 + c >= n) break;
+            double dx[3] = {pj[c].x[0] - pi.x[0], pj[c].x[1] - pi.x[1], pj[c].x[2] - pi.x[2]};
+            min_image(D.g, dx);
+            const double reach = pi.r + pj[c].r + gap;
+            if (dot3(dx, dx) >= reach * reach) continue;
+            pair_interaction(D.p, pi, pj[c], dx, F, T);
+        }
     }
     wall_interaction(D.p, D.g, pi, F, T);
+    const int64_t cap = P.cap;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         P.Fdem[a * cap + i] = F[a];
@@ -1293,24 +1331,24 @@ template <typename R> void launch_part_am(const Desc &D, const Cells<R> &C, hipS
 template <typename R, int MODE> void launch_gather(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
     const bool thin = (D.g.per[0] && D.g.n[0] < 3) || (D.g.per[1] && D.g.n[1] < 3) || (D.g.per[2] && D.g.n[2] < 3);
-    if (thin) {
+    if (thin || D.t.gather == 3) {
         hipLaunchKernelGGL((k_gather_cells<R, MODE>), dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
         return;
     }
     int v = D.t.gather;
     if (v < 0 || v >= kGatherVariants) {
         const double density = D.g.nc > 0 ? (double)D.pt.np / (double)D.g.nc : 0.0;
-        v = density < 0.3 ? 0 : 1;
+        v = density < 0.3 ? 0 : (density < 1.0 ? 1 : 2);
     }
     if (v == 0) {
-        dim3 grid((D.g.n[0] + 15) / 16, (D.g.n[1] + 3) / 4, (D.g.n[2] + 3) / 4);
-        hipLaunchKernelGGL((k_gather_tile<R, MODE, 16, 4, 4, 384>), grid, dim3(256), 0, s, D, C);
+        dim3 grid((D.g.n[0] + 15) / 16, (D.g.n[1] + 3) / 4, (D.g.n[2] + 7) / 8);
+        hipLaunchKernelGGL((k_gather_tile<R, MODE, 16, 4, 4, 2, 256>), grid, dim3(256), 0, s, D, C);
     } else if (v == 1) {
-        dim3 grid((D.g.n[0] + 7) / 8, (D.g.n[1] + 3) / 4, (D.g.n[2] + 3) / 4);
-        hipLaunchKernelGGL((k_gather_tile<R, MODE, 8, 4, 4, 512>), grid, dim3(128), 0, s, D, C);
+        dim3 grid((D.g.n[0] + 15) / 16, (D.g.n[1] + 3) / 4, (D.g.n[2] + 3) / 4);
+        hipLaunchKernelGGL((k_gather_tile<R, MODE, 16, 4, 4, 1, 384>), grid, dim3(256), 0, s, D, C);
     } else {
-        dim3 grid((D.g.n[0] + 7) / 8, (D.g.n[1] + 7) / 8, (D.g.n[2] + 3) / 4);
-        hipLaunchKernelGGL((k_gather_tile<R, MODE, 8, 8, 4, 512>), grid, dim3(256), 0, s, D, C);
+        dim3 grid((D.g.n[0] + 7) / 8, (D.g.n[1] + 3) / 4, (D.g.n[2] + 3) / 4);
+        hipLaunchKernelGGL((k_gather_tile<R, MODE, 8, 4, 4, 1, 640>), grid, dim3(128), 0, s, D, C);
     }
 }
 template <typename R> void launch_gather_am(const Desc &D, const Cells<R> &C, hipStream_t s)

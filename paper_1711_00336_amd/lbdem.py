@@ -21,8 +21,9 @@ FIELD_DRHO, FIELD_J, FIELD_EPS_F, FIELD_F_ACC, FIELD_DUDT, FIELD_GRADP, FIELD_UP
 FIELD_NCOMP = {FIELD_DRHO: 1, FIELD_J: 3, FIELD_EPS_F: 1, FIELD_F_ACC: 3, FIELD_DUDT: 3,
                FIELD_GRADP: 3, FIELD_UPREV: 3, FIELD_PDF: 19}
 FLAG_NO_GRAPH = 1
-KCLASS = {"stream_collide": 0, "moments": 1, "cellfields": 2, "particles": 3, "gathers": 4,
-          "dem": 5, "bins": 6}
+KCLASS = {"stream_collide": 0, "moments": 1, "cellfields": 2, "part_am": 3, "part_drag": 4,
+          "gather_am": 5, "gather_fd": 6, "gather_eps": 7, "nlist": 8, "dem_force": 9,
+          "integrate": 10, "bins": 11}
 
 
 class LbdemError(RuntimeError):
@@ -101,6 +102,7 @@ def lib():
             "lbdem_load_state": (st, [H, C.c_void_p, C.c_size_t]),
             "lbdem_set_timing": (st, [H, C.c_int]),
             "lbdem_autotune": (st, [H, C.POINTER(C.c_int32)]),
+            "lbdem_set_gather_variant": (st, [H, C.c_int32]),
             "lbdem_batch_create": (st, [C.c_int32, C.POINTER(lbdem_params), C.c_void_p, C.POINTER(H)]),
             "lbdem_batch_domain": (st, [H, C.c_int32, C.POINTER(H)]),
             "lbdem_batch_size": (C.c_int32, [H]),
@@ -277,6 +279,9 @@ class Domain:
         v = C.c_int32(-1)
         _check(self.h, lib().lbdem_autotune(self.h, C.byref(v)))
         return v.value
+
+    def lbdem_set_gather_variant(self, variant):
+        _check(self.h, lib().lbdem_set_gather_variant(self.h, int(variant)))
 
     def lbdem_kernel_time(self, cls):
         ms = C.c_double(0.0); n = C.c_int64(0)

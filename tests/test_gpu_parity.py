@@ -95,6 +95,34 @@ def test_parity_periodic_settling_ragged(L):
     _one_step_parity(L, case, warm=3, nsteps=2)
 
 
+@pytest.mark.parametrize("eps", [0.03, 0.12])
+def test_gather_variants_bitwise_equal_and_match_oracle(L, eps):
+    """Every gather variant (LDS tiles of three shapes, tiles too crowded for
+    LDS that fall back to the per-cell gather, and the per-cell gather itself)
+    sums a cell's particles in the same order, so all give the same bits; two
+    steps of them match the oracle. Edge 26 leaves ragged tiles on every axis."""
+    case = I.case_settling(7, 26, eps, 0.8, 2.5, precision="fp64")
+    _say(f"case {case.name} np {case.particles.n}")
+    o = warm_oracle(case, 2, None)
+    states = []
+    for v in range(4):
+        with L.Domain(case.params) as dom:
+            dom.lbdem_set_gather_variant(v)
+            load_oracle_state(dom, o.state)
+            dom.step(2)
+            states.append(dom.lbdem_get_state())
+    o.step(2)
+    errs, bad = compare_states(states[0], o.state, case.params, TOL64)
+    _say(f"  variant 0 vs oracle {errs}")
+    assert not bad, errs
+    for v in range(1, 4):
+        for k, a in states[0].items():
+            assert np.array_equal(np.asarray(states[v][k]), np.asarray(a)), (v, k)
+    with L.Domain(case.params) as dom:
+        with pytest.raises(L.LbdemError):
+            dom.lbdem_set_gather_variant(4)
+
+
 def test_parity_degenerate_thin_periodic_axis(L):
     """A periodic axis of 2 cells: kernel stencils and neighbour bins wrap onto
     themselves."""
