@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 using namespace lbdem;
@@ -309,6 +310,7 @@ void swap_particle_buffers(lbdem_domain_t h)
     std::swap(P.d, P.d2);
     std::swap(P.rho, P.rho2);
     std::swap(P.id, P.id2);
+    std::swap(P.pk, P.pk2);
 }
 
 // bins of the current positions, slots sorted into bin order, stencils
@@ -381,6 +383,15 @@ void alloc_particles(lbdem_domain_t h, int64_t cap)
     hip_check(hipMemsetAsync(P.sw, 0, sizeof(double) * 9 * c, h->stream), "hipMemsetAsync");
     h->list = (int *)h->dalloc(sizeof(int) * c);
     h->list_cap = P.cap;
+    h->dfree(P.pk);
+    h->dfree(P.pk2);
+    P.pk = P.pk2 = nullptr;
+    if (h->prec == LBDEM_FP32_DEV) {
+        P.pk = (DemRec *)h->dalloc(sizeof(DemRec) * c);
+        P.pk2 = (DemRec *)h->dalloc(sizeof(DemRec) * c);
+        hip_check(hipMemsetAsync(P.pk, 0, sizeof(DemRec) * c, h->stream), "hipMemsetAsync");
+        hip_check(hipMemsetAsync(P.pk2, 0, sizeof(DemRec) * c, h->stream), "hipMemsetAsync");
+    }
 }
 
 // host AoS [n][3] <-> device SoA [3][cap]
@@ -518,7 +529,7 @@ void enqueue_step(lbdem_domain_t h)
         launch_cls(h, 6, [&] { launch_gather_fd<R>(h->desc(), C, s); });
         launch_cls(h, 8, [&] { launch_nlist(h->desc(), s); });
         for (int sub = 0; sub < h->phys.n_dem; ++sub) {
-            launch_cls(h, 9, [&] { launch_dem_force(h->desc(), s); });
+            launch_cls(h, 9, [&] { launch_dem_force(h->desc(), std::is_same<R, float>::value, s); });
             launch_cls(h, 10, [&] { launch_integrate(h->desc(), sub == h->phys.n_dem - 1, s); });
         }
         launch_cls(h, 11, [&] { sort_particles(h); });

@@ -56,6 +56,17 @@ struct Bins {
     int *bsum;                  // scan block sums
 };
 
+// Packed copy of what a DEM pair evaluation reads of a neighbour, one 64-byte
+// record per slot (FP32-deviation form only): one cache line per neighbour
+// instead of eleven scattered SoA loads. Positions stay FP64.
+struct alignas(64) DemRec {
+    double x[3];
+    float d, m;
+    float u[3], w[3];
+    float pad[2];
+};
+static_assert(sizeof(DemRec) == 64, "one 64-byte record");
+
 // Particles, SoA: vectors [3][cap] (component a of slot i at a*cap+i).
 // Slots are kept sorted by (cell, original index) after every rebinning, so
 // a bin is a contiguous slot range and neighbouring threads touch
@@ -78,6 +89,7 @@ struct Parts {
     int *nlist, *nnb, *slot_of;
     double *xbuild;
     int *need;                  // 1: rebuild the lists before the next DEM substep
+    DemRec *pk, *pk2;           // packed DEM records by slot (+ permutation target), or null
 };
 
 // launch choices picked per domain (autotuner); -1 = heuristic default
@@ -129,7 +141,7 @@ void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials
                  hipStream_t s);
 int diag_blocks(const Desc &D);
 
-void launch_dem_force(const Desc &D, hipStream_t s);
+void launch_dem_force(const Desc &D, bool fp32_forces, hipStream_t s);  // pair math in FP32 or FP64
 void launch_nlist(const Desc &D, hipStream_t s);      // rebuild Verlet lists if flagged
 void launch_integrate(const Desc &D, int last_substep, hipStream_t s);
 void launch_bin_count(const Desc &D, hipStream_t s);

@@ -284,16 +284,34 @@ __device__ __forceinline__ void load_stencil(const Parts &P, int64_t i, Stencil 
 // st.w[a][o] for a runtime o without indexing a register array
 __device__ __forceinline__ double sel3(const double w[3], int o) { return o == 0 ? w[0] : (o == 1 ? w[1] : w[2]); }
 
+// F_am = C_am rho_f V (Du/Dt|p - a_p) (Table 1); subcycle start state
+template <typename R> __device__ __forceinline__ void am_force(const Desc &D, int64_t i, const R Du[3])
+{
+    const Parts &P = D.pt;
+    const int64_t cap = P.cap;
+    const R V = (R)sphere_volume(P.d[i]);
+    const R cam = (R)(D.p.c_am * D.p.rho_f);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const R F = D.p.use_am ? cam * V * (Du[b] - (R)P.a[b * cap + i]) : (R)0;
+        P.Fam[b * cap + i] = (double)F;
+        P.ustart[b * cap + i] = P.u[b * cap + i];
+        P.xstart[b * cap + i] = P.x[b * cap + i];
+    }
+}
+
+// interpolation sums and the added-mass force in the cell precision R
+// (FP32 in the FP32-deviation form); F_am is stored FP64
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
 {
     const int64_t i = gidx();
     const Parts &P = D.pt;
     if (i >= P.np) return;
-    const int64_t cap = P.cap, nc = D.g.nc;
+    const int64_t nc = D.g.nc;
     Stencil st;
     load_stencil(P, i, st);
-    double Du[3] = {0.0, 0.0, 0.0};
+    R Du[3] = {(R)0, (R)0, (R)0};
 #pragma unroll 1
     for (int oz = 0; oz < 3; ++oz) {
         const int cz = stencil_coord(st.b[2], oz - 1, D.g.n[2], D.g.per[2]);
@@ -304,20 +322,13 @@ __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
             for (int ox = 0; ox < 3; ++ox) {
                 const int cx = stencil_coord(st.b[0], ox - 1, D.g.n[0], D.g.per[0]);
                 const int64_t cell = cidx(D.g, cx, cy, cz);
-                const double w = st.w[0][ox] * st.w[1][oy] * sel3(st.w[2], oz);
+                const R w = (R)(st.w[0][ox] * st.w[1][oy] * sel3(st.w[2], oz));
 #pragma unroll
-                for (int b = 0; b < 3; ++b) Du[b] += w * (double)C.dudt[b * nc + cell];
+                for (int b = 0; b < 3; ++b) Du[b] += w * C.dudt[b * nc + cell];
             }
         }
     }
-    const double V = sphere_volume(P.d[i]);
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        const double F = D.p.use_am ? D.p.c_am * D.p.rho_f * V * (Du[b] - P.a[b * cap + i]) : 0.0;
-        P.Fam[b * cap + i] = F;
-        P.ustart[b * cap + i] = P.u[b * cap + i];
-        P.xstart[b * cap + i] = P.x[b * cap + i];
-    }
+    am_force<R>(D, i, Du);
 }
 
 // ---------------------------------------------------------------------------
@@ -626,26 +637,65 @@ __global__ __launch_bounds__(kBlock) void k_gather_cells(Desc D, Cells<R> C)
 // with u_f re-evaluated from f_ext = eps_f f_b + f_am (Sec. 3.2.3 stability
 // measures; Alg. 1 "Reevaluate u_f").
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double drag_factor(double Re, double ep)
+template <typename T> __device__ __forceinline__ T drag_factor(T Re, T ep)
 {
-    const double e1 = 1.0 - ep;
-    const double cd0 = 1.0 + 0.15 * (Re > 0.0 ? pow(Re, 0.687) : 0.0);
-    const double A = 5.81 * ep / (e1 * e1 * e1) + 0.48 * (ep > 0.0 ? cbrt(ep) : 0.0) / (e1 * e1 * e1 * e1);
-    const double B = ep * ep * ep * Re * (0.95 + 0.61 * ep * ep * ep / (e1 * e1));
-    const double cd = e1 * (cd0 / (e1 * e1 * e1) + A + B);
+    const T e1 = (T)1 - ep;
+    const T cd0 = (T)1 + (T)0.15 * (Re > (T)0 ? pow(Re, (T)0.687) : (T)0);
+    const T A = (T)5.81 * ep / (e1 * e1 * e1) + (T)0.48 * (ep > (T)0 ? cbrt(ep) : (T)0) / (e1 * e1 * e1 * e1);
+    const T B = ep * ep * ep * Re * ((T)0.95 + (T)0.61 * ep * ep * ep / (e1 * e1));
+    const T cd = e1 * (cd0 / (e1 * e1 * e1) + A + B);
     return e1 * cd;
 }
 
+// F_pr = -V grad P|p, F_d (Tenneti closure as the paper prints it, Table 1),
+// gravity and buoyancy; F_const for the DEM substeps
+template <typename R>
+__device__ __forceinline__ void drag_forces(const Desc &D, int64_t i, const R uf[3], const R gp[3], R ep, int record)
+{
+    const Parts &P = D.pt;
+    const int64_t cap = P.cap;
+    const double dd = P.d[i];
+    const R d = (R)dd;
+    const R V = (R)sphere_volume(dd);
+    const R mu = (R)D.p.mu, rho_f = (R)D.p.rho_f;
+    R wv[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) wv[b] = uf[b] - (R)P.u[b * cap + i];
+    const R wn = sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+    const R Re = ((R)1 - ep) * rho_f * d * wn / mu;
+    const R fac = (R)3 * (R)M_PI * d * mu * drag_factor(Re, ep);
+    const R rp = (R)P.rho[i];
+    const int pid = P.id[i];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const R Fpr = -V * gp[b];
+        const R Fd = fac * wv[b];
+        const R fgb = (rp - rho_f) * V * (R)D.p.g[b];
+        const R Fam = (R)P.Fam[b * cap + i];
+        const R Fc = Fd + Fpr + Fam + fgb;
+        P.Fd[b * cap + i] = (double)Fd;
+        P.Fc[b * cap + i] = (double)Fc;
+        if (record) {
+            P.Fam_id[b * cap + pid] = (double)Fam;
+            P.Fd_id[b * cap + pid] = (double)Fd;
+            P.Fpr_id[b * cap + pid] = (double)Fpr;
+            P.Fc_id[b * cap + pid] = (double)Fc;
+        }
+    }
+}
+
+// interpolation sums and the closures in the cell precision R (FP32 in the
+// FP32-deviation form); the forces are stored FP64
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_part_drag(Desc D, Cells<R> C, int record)
 {
     const int64_t i = gidx();
     const Parts &P = D.pt;
     if (i >= P.np) return;
-    const int64_t cap = P.cap, nc = D.g.nc;
+    const int64_t nc = D.g.nc;
     Stencil st;
     load_stencil(P, i, st);
-    double uf[3] = {0.0, 0.0, 0.0}, gp[3] = {0.0, 0.0, 0.0}, ep = 0.0;
+    R uf[3] = {(R)0, (R)0, (R)0}, gp[3] = {(R)0, (R)0, (R)0}, ep = (R)0;
 #pragma unroll 1
     for (int oz = 0; oz < 3; ++oz) {
         const int cz = stencil_coord(st.b[2], oz - 1, D.g.n[2], D.g.per[2]);
@@ -656,175 +706,330 @@ __global__ __launch_bounds__(kBlock) void k_part_drag(Desc D, Cells<R> C, int re
             for (int ox = 0; ox < 3; ++ox) {
                 const int cx = stencil_coord(st.b[0], ox - 1, D.g.n[0], D.g.per[0]);
                 const int64_t cell = cidx(D.g, cx, cy, cz);
-                const double w = st.w[0][ox] * st.w[1][oy] * sel3(st.w[2], oz);
+                const R w = (R)(st.w[0][ox] * st.w[1][oy] * sel3(st.w[2], oz));
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
-                    uf[b] += w * (double)C.uf[b * nc + cell];
-                    gp[b] += w * (double)C.gradp[b * nc + cell];
+                    uf[b] += w * C.uf[b * nc + cell];
+                    gp[b] += w * C.gradp[b * nc + cell];
                 }
-                ep += w * (double)C.epsp[cell];
+                ep += w * C.epsp[cell];
             }
         }
     }
-    const double d = P.d[i];
-    const double V = sphere_volume(d);
-    double wv[3];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) wv[b] = uf[b] - P.u[b * cap + i];
-    const double wn = sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
-    const double Re = (1.0 - ep) * D.p.rho_f * d * wn / D.p.mu;
-    const double fac = 3.0 * M_PI * d * D.p.mu * drag_factor(Re, ep);
-    const double rp = P.rho[i];
-    const int pid = P.id[i];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-        const double Fpr = -V * gp[b];
-        const double Fd = fac * wv[b];
-        const double fgb = (rp - D.p.rho_f) * V * D.p.g[b];
-        const double Fam = P.Fam[b * cap + i];
-        const double Fc = Fd + Fpr + Fam + fgb;
-        P.Fd[b * cap + i] = Fd;
-        P.Fc[b * cap + i] = Fc;
-        if (record) {
-            P.Fam_id[b * cap + pid] = Fam;
-            P.Fd_id[b * cap + pid] = Fd;
-            P.Fpr_id[b * cap + pid] = Fpr;
-            P.Fc_id[b * cap + pid] = Fc;
+    drag_forces<R>(D, i, uf, gp, ep, record);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-tiled particle pass (a6 drag/pressure/gravity; the template also
+// covers a4's added mass, which runs per particle). A workgroup owns the particles whose bins lie in a TX x TY x TZ tile of cells
+// (one contiguous slot range per x-row of bins). It loads the cell fields of
+// the tile widened by one cell (wrapped on periodic axes, clamped on walled
+// ones, as the per-particle stencil does) into LDS with coalesced loads, and
+// every particle interpolates from LDS. The arithmetic and its order are
+// those of k_part_am / k_part_drag, so the results are bit-identical.
+// ---------------------------------------------------------------------------
+enum { PASS_AM = 0, PASS_DRAG = 1 };
+
+template <typename R, int PASS, int TX, int TY, int TZ>
+__global__ __launch_bounds__(256) void k_part_tile(Desc D, Cells<R> C, int record)
+{
+    constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, NHC = HX * HY * HZ;
+    constexpr int NV = PASS == PASS_AM ? 3 : 7;  // Du/Dt | u_f, grad P, eps_p
+    constexpr int NR = TY * TZ;
+    static_assert(NR <= 64, "rows of one tile are scanned by one wavefront");
+    __shared__ R cv[NV][NHC];
+    __shared__ int rp[NR + 1], rsrc[NR];
+
+    const int tid = threadIdx.x;
+    const int n0 = D.g.n[0], n1 = D.g.n[1], n2 = D.g.n[2];
+    const int64_t nc = D.g.nc;
+    const uint32_t lin = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                   gridDim.x * gridDim.y * gridDim.z);
+    const int bx = (int)(lin % gridDim.x), by = (int)((lin / gridDim.x) % gridDim.y),
+              bz = (int)(lin / (gridDim.x * gridDim.y));
+    const int x0 = bx * TX, y0 = by * TY, z0 = bz * TZ;
+    const int xe = min(x0 + TX, n0);
+    const int lx = xe - x0 + 1, ly = min(y0 + TY, n1) - y0 + 1, lz = min(z0 + TZ, n2) - z0 + 1;
+
+    // own particles: one slot range per row of bins
+    if (tid < 64) {
+        int cnt = 0, src = 0;
+        if (tid < NR) {
+            const int y = y0 + tid % TY, z = z0 + tid / TY;
+            if (y < n1 && z < n2) {
+                src = D.b.start[cidx(D.g, x0, y, z)];
+                cnt = D.b.start[cidx(D.g, xe - 1, y, z) + 1] - src;
+            }
+            rsrc[tid] = src;
         }
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int y = __shfl_up(incl, off, 64);
+            if ((tid & 63) >= off) incl += y;
+        }
+        if (tid < NR) rp[tid] = incl - cnt;
+        if (tid == NR - 1) rp[NR] = incl;
+    }
+    // halo cell fields
+    for (int hc = tid; hc < NHC; hc += 256) {
+        const int hx = hc % HX, hy = (hc / HX) % HY, hz = hc / (HX * HY);
+        R v[NV];
+        if (hx <= lx && hy <= ly && hz <= lz) {
+            const int gx = stencil_coord(x0, hx - 1, n0, D.g.per[0]);
+            const int gy = stencil_coord(y0, hy - 1, n1, D.g.per[1]);
+            const int gz = stencil_coord(z0, hz - 1, n2, D.g.per[2]);
+            const int64_t cell = cidx(D.g, gx, gy, gz);
+            if (PASS == PASS_AM) {
+#pragma unroll
+                for (int b = 0; b < 3; ++b) v[b] = C.dudt[b * nc + cell];
+            } else {
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    v[b] = C.uf[b * nc + cell];
+                    v[3 + b] = C.gradp[b * nc + cell];
+                }
+                v[6] = C.epsp[cell];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NV; ++t) v[t] = (R)0;
+        }
+#pragma unroll
+        for (int t = 0; t < NV; ++t) cv[t][hc] = v[t];
+    }
+    __syncthreads();
+
+    const Parts &P = D.pt;
+    const int K = rp[NR];
+    for (int k = tid; k < K; k += 256) {
+        int lo = 0, hi = NR - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rp[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t i = rsrc[lo] + (k - rp[lo]);
+        Stencil st;
+        load_stencil(P, i, st);
+        // the stencil base is the particle's bin, inside this tile; the clamp
+        // only keeps LDS indices in range for a particle already flagged as
+        // having left the domain
+        const int hx0 = min(max(st.b[0] - x0, 0), TX - 1), hy0 = min(max(st.b[1] - y0, 0), TY - 1),
+                  hz0 = min(max(st.b[2] - z0, 0), TZ - 1);
+        R acc[NV];
+#pragma unroll
+        for (int t = 0; t < NV; ++t) acc[t] = (R)0;
+#pragma unroll 1
+        for (int oz = 0; oz < 3; ++oz) {
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) {
+#pragma unroll
+                for (int ox = 0; ox < 3; ++ox) {
+                    const int hc = ((hz0 + oz) * HY + (hy0 + oy)) * HX + (hx0 + ox);
+                    const R w = (R)(st.w[0][ox] * st.w[1][oy] * sel3(st.w[2], oz));
+                    if (PASS == PASS_AM) {
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) acc[b] += w * cv[b][hc];
+                    } else {
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            acc[b] += w * cv[b][hc];
+                            acc[3 + b] += w * cv[3 + b][hc];
+                        }
+                        acc[6] += w * cv[6][hc];
+                    }
+                }
+            }
+        }
+        if (PASS == PASS_AM) am_force<R>(D, i, acc);
+        else drag_forces<R>(D, i, acc, acc + 3, acc[6], record);
     }
 }
 
 // ---------------------------------------------------------------------------
 // a8: DEM (Sec. 3.1.1) + lubrication (Sec. 3.1.3) forces of one substep.
 // ---------------------------------------------------------------------------
-struct PV {
-    double r, m, d;
-    double x[3], u[3], w[3];
+// Pair and wall forces are evaluated in the compute type T: double for the
+// FP64 path, float in the FP32-deviation form (positions, their differences
+// and the integration stay FP64 in both).
+template <typename T> struct PV {
+    T r, m, d;
+    double x[3];
+    T u[3], w[3];
 };
 
-__device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3])
+template <typename T> __device__ __forceinline__ void cross3(const T a[3], const T b[3], T c[3])
 {
     c[0] = a[1] * b[2] - a[2] * b[1];
     c[1] = a[2] * b[0] - a[0] * b[2];
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
-__device__ __forceinline__ double dot3(const double a[3], const double b[3])
+template <typename T> __device__ __forceinline__ T dot3(const T a[3], const T b[3])
 {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
 // spring-dashpot normal force and Coulomb-limited tangential force; torque
 // about the centre is (d_i/2) n x F^t (the moment of F^t at the contact point)
-__device__ __forceinline__ void contact(const Phys &p, double delta, const double n[3], const double ur[3],
-                                        double mij, double ri, double F[3], double T[3])
+template <typename T>
+__device__ __forceinline__ void contact(const Phys &p, T delta, const T n[3], const T ur[3], T mij, T ri, T F[3],
+                                        T Tq[3])
 {
-    const double kn = mij * p.kn_per_m;
-    const double xi = mij * p.xi_per_m;
-    const double urn_s = dot3(ur, n);
-    double urn[3], urt[3], Fn[3];
+    const T kn = mij * (T)p.kn_per_m;
+    const T xi = mij * (T)p.xi_per_m;
+    const T urn_s = dot3(ur, n);
+    T urn[3], urt[3], Fn[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         urn[a] = urn_s * n[a];
         urt[a] = ur[a] - urn[a];
         Fn[a] = -kn * delta * n[a] - xi * urn[a];
     }
-    const double urt_n = sqrt(dot3(urt, urt));
-    double Ft[3] = {0.0, 0.0, 0.0};
-    if (urt_n > 0.0) {
-        const double fn_n = sqrt(dot3(Fn, Fn));
-        const double mag = fmin(p.mu_c * fn_n, xi * urt_n);
+    const T urt_n = sqrt(dot3(urt, urt));
+    T Ft[3] = {(T)0, (T)0, (T)0};
+    if (urt_n > (T)0) {
+        const T fn_n = sqrt(dot3(Fn, Fn));
+        const T mag = fmin((T)p.mu_c * fn_n, xi * urt_n);
 #pragma unroll
         for (int a = 0; a < 3; ++a) Ft[a] = -mag * urt[a] / urt_n;
     }
-    double tq[3];
+    T tq[3];
     cross3(n, Ft, tq);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         F[a] += Fn[a] + Ft[a];
-        T[a] += ri * tq[a];
+        Tq[a] += ri * tq[a];
     }
 }
 
 // Eq. lubrication_force, applied for h < h_c with h := max(h, h_min) and,
 // when lub_stab is set, h >= 3 pi mu <d>^2 dt_DEM / (8 m_ij)
-__device__ __forceinline__ void lubrication(const Phys &p, double h, double dm, double mij, const double n[3],
-                                            const double upr[3], double F[3])
+template <typename T>
+__device__ __forceinline__ void lubrication(const Phys &p, T h, T dm, T mij, const T n[3], const T upr[3], T F[3])
 {
-    if (!(h < p.h_c)) return;
-    const double mu = p.mu;
-    double he = fmax(h, p.h_min);
-    if (p.lub_stab) he = fmax(he, 3.0 * M_PI * mu * dm * dm * p.dt_dem / (8.0 * mij));
-    const double Lg = log(dm / (2.0 * he));
-    const double asq = 1.5 * M_PI * mu * dm * (dm / (4.0 * he) + (18.0 / 40.0) * Lg + (9.0 / 84.0) * (he / dm) * Lg);
-    const double ash = 0.5 * M_PI * mu * dm * Lg * (dm + he) * (dm + he) / 4.0;
-    const double un = dot3(upr, n);
-    const double s = 2.0 / (he + dm);
+    if (!(h < (T)p.h_c)) return;
+    const T mu = (T)p.mu;
+    const T pi = (T)M_PI;
+    T he = fmax(h, (T)p.h_min);
+    if (p.lub_stab) he = fmax(he, (T)3 * pi * mu * dm * dm * (T)p.dt_dem / ((T)8 * mij));
+    const T Lg = log(dm / ((T)2 * he));
+    const T asq = (T)1.5 * pi * mu * dm * (dm / ((T)4 * he) + ((T)18 / (T)40) * Lg + ((T)9 / (T)84) * (he / dm) * Lg);
+    const T ash = (T)0.5 * pi * mu * dm * Lg * (dm + he) * (dm + he) / (T)4;
+    const T un = dot3(upr, n);
+    const T s = (T)2 / (he + dm);
 #pragma unroll
     for (int a = 0; a < 3; ++a) F[a] += -asq * un * n[a] - ash * s * s * (upr[a] - un * n[a]);
 }
 
-__device__ __forceinline__ void pair_interaction(const Phys &p, const PV &pi, const PV &pj, const double dx[3],
-                                                 double F[3], double T[3])
+template <typename T>
+__device__ __forceinline__ void pair_interaction(const Phys &p, const PV<T> &pi, const PV<T> &pj, const T dx[3],
+                                                 T F[3], T Tq[3])
 {
-    const double dist2 = dot3(dx, dx);
-    const double reach = pi.r + pj.r + (p.use_lub ? fmax(p.h_c, 0.0) : 0.0);
+    const T dist2 = dot3(dx, dx);
+    const T reach = pi.r + pj.r + (p.use_lub ? (T)fmax(p.h_c, 0.0) : (T)0);
     if (dist2 >= reach * reach) return;
-    const double dist = sqrt(dist2);
-    const double n[3] = {dx[0] / dist, dx[1] / dist, dx[2] / dist};
-    const double delta = pi.r + pj.r - dist;
-    const double mij = pi.m * pj.m / (pi.m + pj.m);
-    if (delta > 0.0) {
-        double s[3], ur[3];
+    const T dist = sqrt(dist2);
+    const T n[3] = {dx[0] / dist, dx[1] / dist, dx[2] / dist};
+    const T delta = pi.r + pj.r - dist;
+    const T mij = pi.m * pj.m / (pi.m + pj.m);
+    if (delta > (T)0) {
+        T s[3], ur[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) s[a] = pi.r * pi.w[a] + pj.r * pj.w[a];
         cross3(s, n, ur);
 #pragma unroll
         for (int a = 0; a < 3; ++a) ur[a] += pi.u[a] - pj.u[a];
-        contact(p, delta, n, ur, mij, pi.r, F, T);
+        contact(p, delta, n, ur, mij, pi.r, F, Tq);
     }
     if (p.use_lub) {
-        const double dm = 2.0 * pi.d * pj.d / (pi.d + pj.d);
-        const double upr[3] = {pi.u[0] - pj.u[0], pi.u[1] - pj.u[1], pi.u[2] - pj.u[2]};
+        const T dm = (T)2 * pi.d * pj.d / (pi.d + pj.d);
+        const T upr[3] = {pi.u[0] - pj.u[0], pi.u[1] - pj.u[1], pi.u[2] - pj.u[2]};
         lubrication(p, -delta, dm, mij, n, upr, F);
     }
 }
 
-__device__ __forceinline__ void wall_interaction(const Phys &p, const Geo &g, const PV &pi, double F[3],
-                                                 double T[3])
+template <typename T>
+__device__ __forceinline__ void wall_interaction(const Phys &p, const Geo &g, const PV<T> &pi, T F[3], T Tq[3])
 {
     for (int a = 0; a < 3; ++a) {
         if (g.per[a]) continue;
         for (int side = 0; side < 2; ++side) {
-            const double dist = side == 0 ? pi.x[a] : (double)g.n[a] - pi.x[a];
-            double n[3] = {0.0, 0.0, 0.0};
-            n[a] = side == 0 ? -1.0 : 1.0;
-            const double delta = pi.r - dist;
-            if (delta > 0.0) {
-                double s[3], ur[3];
+            const T dist = (T)(side == 0 ? pi.x[a] : (double)g.n[a] - pi.x[a]);
+            T n[3] = {(T)0, (T)0, (T)0};
+            n[a] = side == 0 ? (T)-1 : (T)1;
+            const T delta = pi.r - dist;
+            if (delta > (T)0) {
+                T s[3], ur[3];
 #pragma unroll
                 for (int b = 0; b < 3; ++b) s[b] = pi.r * pi.w[b];
                 cross3(s, n, ur);
 #pragma unroll
                 for (int b = 0; b < 3; ++b) ur[b] += pi.u[b];
-                contact(p, delta, n, ur, pi.m, pi.r, F, T);
+                contact(p, delta, n, ur, pi.m, pi.r, F, Tq);
             }
-            if (p.use_lub) lubrication(p, -delta, 2.0 * pi.d, pi.m, n, pi.u, F);
+            if (p.use_lub) lubrication(p, -delta, (T)2 * pi.d, pi.m, n, pi.u, F);
         }
     }
 }
 
-__device__ __forceinline__ void load_pv(const Parts &P, int64_t i, PV &v)
+template <typename T> __device__ __forceinline__ void load_pv(const Parts &P, int64_t i, PV<T> &v)
 {
     const int64_t cap = P.cap;
-    v.d = P.d[i];
-    v.r = 0.5 * v.d;
-    v.m = P.rho[i] * sphere_volume(v.d);
+    const double d = P.d[i];
+    v.d = (T)d;
+    v.r = (T)(0.5 * d);
+    v.m = (T)(P.rho[i] * sphere_volume(d));
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         v.x[a] = P.x[a * cap + i];
-        v.u[a] = P.u[a * cap + i];
-        v.w[a] = P.w[a * cap + i];
+        v.u[a] = (T)P.u[a * cap + i];
+        v.w[a] = (T)P.w[a * cap + i];
     }
+}
+
+__device__ __forceinline__ void store_rec(DemRec *pk, int64_t i, const double x[3], const double u[3],
+                                          const double w[3], double d, double rho)
+{
+    DemRec r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.x[a] = x[a];
+        r.u[a] = (float)u[a];
+        r.w[a] = (float)w[a];
+    }
+    r.d = (float)d;
+    r.m = (float)(rho * sphere_volume(d));
+    r.pad[0] = r.pad[1] = 0.0f;
+    const uint4 *src = reinterpret_cast<const uint4 *>(&r);
+    uint4 *dst = reinterpret_cast<uint4 *>(pk + i);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[k] = src[k];
+}
+
+// the same values load_pv<float> gives, from one 64-byte record
+__device__ __forceinline__ void load_rec(const DemRec *pk, int64_t i, PV<float> &v)
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(pk + i);
+    DemRec r;
+    uint4 *dst = reinterpret_cast<uint4 *>(&r);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) dst[k] = src[k];
+    v.d = r.d;
+    v.r = 0.5f * r.d;
+    v.m = r.m;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        v.x[a] = r.x[a];
+        v.u[a] = r.u[a];
+        v.w[a] = r.w[a];
+    }
+}
+
+template <typename T> __device__ __forceinline__ void load_particle(const Parts &P, int64_t i, PV<T> &v)
+{
+    if constexpr (sizeof(T) == 4) load_rec(P.pk, i, v);
+    else load_pv(P, i, v);
 }
 
 __device__ __forceinline__ void min_image(const Geo &g, double dx[3])
@@ -903,50 +1108,50 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
 }
 
 // contact + lubrication force and torque on every particle from its list.
-// The list is walked in chunks of kChunk entries whose indices, slots and
-// particle data are requested together, so their memory latencies overlap;
-// pairs are still summed in list order.
-constexpr int kChunk = 4;
-static_assert(kNbr % kChunk == 0, "list rows hold whole chunks");
+// The list is walked in chunks of entries (4 in FP32, 2 in FP64, to bound
+// register use) whose indices, slots and particle data are requested
+// together, so their memory latencies overlap; pairs are still summed in
+// list order.
 
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
 {
     const Parts &P = D.pt;
     const int64_t i = gidx();
     if (i == 0) *P.need = 0;  // lists are current for this subcycle
     if (i >= P.np) return;
-    PV pi;
-    load_pv(P, i, pi);
-    double F[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
-    const double gap = D.p.use_lub ? fmax(D.p.h_c, 0.0) : 0.0;
+    PV<T> pi;
+    load_particle(P, i, pi);
+    T F[3] = {(T)0, (T)0, (T)0}, Tq[3] = {(T)0, (T)0, (T)0};
+    const T gap = D.p.use_lub ? (T)fmax(D.p.h_c, 0.0) : (T)0;
     const int me = P.id[i];
     const int n = P.nnb[me];
     const int *L = P.nlist + (int64_t)me * kNbr;
+    constexpr int kChunk = sizeof(T) == 4 ? 4 : 2;
     for (int t0 = 0; t0 < n; t0 += kChunk) {
-        const int4 ids = *reinterpret_cast<const int4 *>(L + t0);
-        const int idv[kChunk] = {ids.x, ids.y, ids.z, ids.w};
         int js[kChunk];
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) js[c] = t0 + c < n ? P.slot_of[idv[c]] : (int)i;
-        PV pj[kChunk];
+        for (int c = 0; c < kChunk; ++c) js[c] = t0 + c < n ? P.slot_of[L[t0 + c]] : (int)i;
+        PV<T> pj[kChunk];
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) load_pv(P, js[c], pj[c]);
+        for (int c = 0; c < kChunk; ++c) load_particle(P, js[c], pj[c]);
 #pragma unroll
         for (int c = 0; c < kChunk; ++c) {
             if (t0 + c >= n) break;
-            double dx[3] = {pj[c].x[0] - pi.x[0], pj[c].x[1] - pi.x[1], pj[c].x[2] - pi.x[2]};
-            min_image(D.g, dx);
-            const double reach = pi.r + pj[c].r + gap;
+            double dxd[3] = {pj[c].x[0] - pi.x[0], pj[c].x[1] - pi.x[1], pj[c].x[2] - pi.x[2]};
+            min_image(D.g, dxd);
+            const T dx[3] = {(T)dxd[0], (T)dxd[1], (T)dxd[2]};
+            const T reach = pi.r + pj[c].r + gap;
             if (dot3(dx, dx) >= reach * reach) continue;
-            pair_interaction(D.p, pi, pj[c], dx, F, T);
+            pair_interaction(D.p, pi, pj[c], dx, F, Tq);
         }
     }
-    wall_interaction(D.p, D.g, pi, F, T);
+    wall_interaction(D.p, D.g, pi, F, Tq);
     const int64_t cap = P.cap;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        P.Fdem[a * cap + i] = F[a];
-        P.Tdem[a * cap + i] = T[a];
+        P.Fdem[a * cap + i] = (double)F[a];
+        P.Tdem[a * cap + i] = (double)Tq[a];
     }
 }
 
@@ -996,6 +1201,11 @@ __global__ __launch_bounds__(kBlock) void k_integrate(Desc D, int last)
         }
     }
     if (bad) atomicOr(D.flags, bad);
+    if (P.pk) {
+        const double uu[3] = {P.u[i], P.u[cap + i], P.u[2 * cap + i]};
+        const double ww[3] = {P.w[i], P.w[cap + i], P.w[2 * cap + i]};
+        store_rec(P.pk, i, x, uu, ww, d, P.rho[i]);
+    }
     // with at most `skin` per subcycle, rebuilding once any particle has moved
     // vskin/2 - skin keeps every pair within the list reach until the rebuild
     if (last && moved > 0.5 * D.p.vskin - D.p.skin) *P.need = 1;
@@ -1123,25 +1333,30 @@ __global__ __launch_bounds__(kBlock) void k_permute(Desc D)
     if (s >= P.np) return;
     const int64_t cap = P.cap;
     const int src = D.b.list[s];
+    double x[3], u[3], w[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double xa = P.x[a * cap + src];
-        P.x2[a * cap + s] = xa;
-        P.u2[a * cap + s] = P.u[a * cap + src];
-        P.w2[a * cap + s] = P.w[a * cap + src];
+        x[a] = P.x[a * cap + src];
+        u[a] = P.u[a * cap + src];
+        w[a] = P.w[a * cap + src];
+        P.x2[a * cap + s] = x[a];
+        P.u2[a * cap + s] = u[a];
+        P.w2[a * cap + s] = w[a];
         P.a2[a * cap + s] = P.a[a * cap + src];
         int b;
-        double w[3];
-        axis_weights(xa, D.g.n[a], D.g.per[a], b, w);
+        double wt[3];
+        axis_weights(x[a], D.g.n[a], D.g.per[a], b, wt);
         P.sb[a * cap + s] = b;
 #pragma unroll
-        for (int o = 0; o < 3; ++o) P.sw[(3 * a + o) * cap + s] = w[o];
+        for (int o = 0; o < 3; ++o) P.sw[(3 * a + o) * cap + s] = wt[o];
     }
-    P.d2[s] = P.d[src];
-    P.rho2[s] = P.rho[src];
+    const double d = P.d[src], rho = P.rho[src];
+    P.d2[s] = d;
+    P.rho2[s] = rho;
     const int pid = P.id[src];
     P.id2[s] = pid;
     P.slot_of[pid] = (int)s;
+    if (P.pk2) store_rec(P.pk2, s, x, u, w, d, rho);
 }
 
 // ---------------------------------------------------------------------------
@@ -1150,15 +1365,12 @@ __global__ __launch_bounds__(kBlock) void k_permute(Desc D)
 // cell, writes the post-collision values to x + c_q. Links leaving through a
 // wall reflect in place into the opposite direction (half-way bounce-back).
 // ---------------------------------------------------------------------------
+// GNS-BGK collision with Guo forcing of one cell (the post-collision values
+// of all 19 directions, before streaming)
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_stream_collide(Desc D, Cells<R> C)
+__device__ __forceinline__ void collide_cell(const Desc &D, const Cells<R> &C, int64_t c, R post[19])
 {
     const int64_t nc = D.g.nc;
-    const int64_t c = gidx();
-    if (c == 0) *D.stepc += 1;
-    if (c >= nc) return;
-    int i, j, k;
-    cell_coords(D.g, c, i, j, k);
     R f[19];
 #pragma unroll
     for (int q = 0; q < 19; ++q) f[q] = C.df_src[q * nc + c];
@@ -1180,7 +1392,6 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(Desc D, Cells<R> C)
     const R uu = ux * ux + uy * uy + uz * uz;
     const R om = (R)D.p.omega;
     const R pre = (R)(1.0 - 0.5 / D.p.tau);
-    const bool wall_x = !D.g.per[0], wall_y = !D.g.per[1], wall_z = !D.g.per[2];
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
         const R cu = (R)CX(q) * ux + (R)CY(q) * uy + (R)CZ(q) * uz;
@@ -1190,7 +1401,27 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(Desc D, Cells<R> C)
         const R gy = (R)3 * (R)CY(q) - (R)3 * uy * ieps + (R)9 * cu * (R)CY(q) * ieps;
         const R gz = (R)3 * (R)CZ(q) - (R)3 * uz * ieps + (R)9 * cu * (R)CZ(q) * ieps;
         const R F = w * pre * (gx * fx + gy * fy + gz * fz);
-        const R post = f[q] + (feq - f[q]) * om + F;
+        post[q] = f[q] + (feq - f[q]) * om + F;
+    }
+}
+
+// push streaming: direction q of cell (i, j, k) goes to (i, j, k) + c_q,
+// wrapped on periodic axes; where it would leave through a wall it returns
+// into the opposite direction of the same cell (half-way bounce-back)
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_stream_collide(Desc D, Cells<R> C)
+{
+    const int64_t nc = D.g.nc;
+    const int64_t c = gidx();
+    if (c == 0) *D.stepc += 1;
+    if (c >= nc) return;
+    int i, j, k;
+    cell_coords(D.g, c, i, j, k);
+    R post[19];
+    collide_cell<R>(D, C, c, post);
+    const bool wall_x = !D.g.per[0], wall_y = !D.g.per[1], wall_z = !D.g.per[2];
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
         int t0 = i + CX(q), t1 = j + CY(q), t2 = k + CZ(q);
         bool wall = false;
         if (CX(q) != 0 && (t0 < 0 || t0 >= D.g.n[0])) {
@@ -1202,8 +1433,8 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(Desc D, Cells<R> C)
         if (CZ(q) != 0 && (t2 < 0 || t2 >= D.g.n[2])) {
             if (wall_z) wall = true; else t2 = t2 < 0 ? t2 + D.g.n[2] : t2 - D.g.n[2];
         }
-        if (wall) C.df_dst[OPP(q) * nc + c] = post;
-        else C.df_dst[q * nc + cidx(D.g, t0, t1, t2)] = post;
+        if (wall) C.df_dst[OPP(q) * nc + c] = post[q];
+        else C.df_dst[q * nc + cidx(D.g, t0, t1, t2)] = post[q];
     }
 }
 
@@ -1320,6 +1551,8 @@ template <typename R> void launch_cellfields(const Desc &D, const Cells<R> &C, h
 {
     hipLaunchKernelGGL(k_cellfields<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
 }
+// added-mass pass: one thread per particle (its 3-component stencil reads
+// are cheap enough that LDS staging of the halo does not pay)
 template <typename R> void launch_part_am(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
     if (D.pt.np > 0) hipLaunchKernelGGL(k_part_am<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
@@ -1355,9 +1588,17 @@ template <typename R> void launch_gather_am(const Desc &D, const Cells<R> &C, hi
 {
     launch_gather<R, MODE_AM>(D, C, s);
 }
+// drag/pressure pass: LDS tiles of 16 x 4 x 8 cells, or one thread per
+// particle reading its stencil cells from global memory (gather variant 3)
 template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, int record, hipStream_t s)
 {
-    if (D.pt.np > 0) hipLaunchKernelGGL(k_part_drag<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C, record);
+    if (D.pt.np == 0) return;
+    if (D.t.gather == 3) {
+        hipLaunchKernelGGL(k_part_drag<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C, record);
+        return;
+    }
+    dim3 grid((D.g.n[0] + 15) / 16, (D.g.n[1] + 3) / 4, (D.g.n[2] + 7) / 8);
+    hipLaunchKernelGGL((k_part_tile<R, PASS_DRAG, 16, 4, 8>), grid, dim3(256), 0, s, D, C, record);
 }
 template <typename R> void launch_gather_fd(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
@@ -1404,9 +1645,11 @@ void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, (const double *)partials, nblk, out);
 }
 
-void launch_dem_force(const Desc &D, hipStream_t s)
+void launch_dem_force(const Desc &D, bool fp32, hipStream_t s)
 {
-    if (D.pt.np > 0) hipLaunchKernelGGL(k_dem_force, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+    if (D.pt.np == 0) return;
+    if (fp32) hipLaunchKernelGGL(k_dem_force<float>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+    else hipLaunchKernelGGL(k_dem_force<double>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
 }
 void launch_nlist(const Desc &D, hipStream_t s)
 {
