@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Throughput of the coupled LBM-DEM time step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dilute|dilute64|small]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dilute|dilute64|small|dense]
     python bench.py --mode batch [--domains 256] [--steps K]
     python bench.py --mode serve [--requests R] [--rates 10,100]
 
@@ -74,20 +74,26 @@ def workload(name, seed):
         return I.case_dilute_periodic(seed, n=128, eps_p=0.05, d=0.8, precision="fp64")
     if name == "small":
         return I.case_small_walled(seed)
+    if name == "dense":
+        say = lambda msg: print(f"[bench] packing: {msg}", file=sys.stderr, flush=True)
+        return I.case_dense_walled(seed, n=(256, 256, 512), eps_p=0.4, precision="fp32dev", progress=say)
     raise SystemExit(f"unknown workload {name}")
 
 
-def mean_list_length(case, vskin=0.4):
+def mean_list_length(case, vskin=0.4, max_query=100000):
     """Mean Verlet-list length of the initial packing: neighbours within
-    (d_i + d_j)/2 + h_c + skin (the list reach of the DEM kernels)."""
+    (d_i + d_j)/2 + h_c + skin (the list reach of the DEM kernels), over all
+    particles or an evenly spaced sample of max_query of them."""
     from paper_1711_00336_amd import inputs as I
     P, p = case.particles, case.params
     if P.n < 2:
         return 0.0
     h = max(p.h_c, 0.0) if p.use_lub else 0.0
     cut = lambda i, j: 0.5 * (P.d[i] + P.d[j]) + h + vskin
-    I_, _J, _dv = I._neighbour_pairs(P.x, list(p.n), list(p.periodic), float(P.d.max()) + h + vskin, cut)
-    return 2.0 * len(I_) / P.n
+    g = I._Grid(P.x, [float(v) for v in p.n], list(p.periodic), float(P.d.max()) + h + vskin)
+    q = np.arange(P.n) if P.n <= max_query else np.linspace(0, P.n - 1, max_query).astype(np.int64)
+    I_, _J, _dv = g.pairs(q, cut)
+    return len(I_) / len(q)
 
 
 def kernel_bytes(case, nlist):
@@ -189,7 +195,10 @@ def cpu_baseline(case, budget_s=20.0):
     if not os.path.exists(O._LIB):
         O.build(force=False)
     p = case.params
-    if case.name.startswith("periodic"):
+    if case.name.startswith("dense"):
+        sample = I.case_dense_walled(0, n=(32, 32, 64), eps_p=0.4, precision="fp64")
+        desc = f"32x32x64 sub-box of the dense workload, {sample.particles.n} spheres"
+    elif case.name.startswith("periodic"):
         eps = float(case.name.split("eps")[-1])
         d = float(case.particles.d[0])
         rr = float(case.particles.rho_p[0])
@@ -404,10 +413,11 @@ def main():
     ap.add_argument("--no-k10", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     args = ap.parse_args()
+    dense = args.mode == "step" and args.workload == "dense"
     if args.steps is None:
-        args.steps = {"step": 200, "batch": 20, "serve": 0}[args.mode]
+        args.steps = 10 if dense else {"step": 200, "batch": 20, "serve": 0}[args.mode]
     if args.warmup is None:
-        args.warmup = {"step": 20, "batch": 3, "serve": 0}[args.mode]
+        args.warmup = 3 if dense else {"step": 20, "batch": 3, "serve": 0}[args.mode]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the spatial decomposition across GPUs is a design, not part of this build)", file=sys.stderr)
@@ -442,10 +452,13 @@ def main():
     print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
 
     # per-kernel-class device time (HIP events on the library's stream)
-    ksteps = max(5, min(args.steps, 20))
+    ksteps = 3 if dense else max(5, min(args.steps, 20))
     dom.lbdem_set_timing(True)
-    dom.lbdem_step(ksteps)
-    dom.lbdem_sync()
+    for k in range(ksteps):
+        dom.lbdem_step(1)
+        dom.lbdem_sync()
+        if dense or k == ksteps - 1:
+            print(f"[bench] per-kernel timing: step {k + 1}/{ksteps}", file=sys.stderr, flush=True)
     times = {}
     for name in lbdem.KCLASS:
         ms, n = dom.lbdem_kernel_time(name)
@@ -456,6 +469,7 @@ def main():
     dom.close()
 
     nlist = mean_list_length(case)
+    print(f"[bench] mean Verlet-list length {nlist:.2f}", file=sys.stderr, flush=True)
     kb = kernel_bytes(case, nlist)
     dom_cls = max((k for k in kb if times[k]["launches_per_step"] > 0), key=lambda k: times[k]["ms_per_step"])
     kt = times[dom_cls]

@@ -66,6 +66,7 @@ struct lbdem_domain {
     // bins
     int *cnt = nullptr, *start = nullptr, *list = nullptr, *bsum = nullptr;
     int64_t list_cap = 0;
+    int64_t nlist_rows = 0;     // particle rows the Verlet-list buffer holds
     // particles
     Parts pt{};
     double dmax = 0.0;
@@ -287,6 +288,24 @@ void update_search(lbdem_domain_t h)
     if (P.rbin > 8) throw std::runtime_error("interaction reach d_max + h_c exceeds the 8-cell search limit");
 }
 
+// Verlet-list capacity per particle: twice the mean number of neighbours
+// within the list reach (d_max + h_c + skin) at the domain's mean particle
+// density, plus 24; a particle with more neighbours raises FLAG_NLIST
+void ensure_lists(lbdem_domain_t h)
+{
+    Parts &P = h->pt;
+    const Phys &ph = h->phys;
+    const double reach = h->dmax + (ph.use_lub ? std::max(ph.h_c, 0.0) : 0.0) + ph.vskin;
+    const double dens = (double)P.np / (double)h->geo.nc;
+    int need = (int)std::ceil(2.0 * dens * (4.0 / 3.0) * M_PI * reach * reach * reach) + 24;
+    need = std::min(std::max((need + 3) & ~3, 32), 4096);
+    if (P.nlist && need <= P.nbr && h->nlist_rows >= P.cap) return;
+    h->dfree(P.nlist);
+    P.nbr = std::max(need, P.nbr);
+    P.nlist = (int *)h->dalloc(sizeof(int) * (size_t)P.nbr * (size_t)P.cap);
+    h->nlist_rows = P.cap;
+}
+
 void update_body_force(lbdem_domain_t h, const std::vector<double> &d, const std::vector<double> &rho)
 {
     const lbdem_params &p = h->prm;
@@ -371,7 +390,9 @@ void alloc_particles(lbdem_domain_t h, int64_t cap)
     }
     for (int **v : {&P.nlist, &P.nnb, &P.slot_of}) h->dfree(*v);
     h->dfree(P.xbuild);
-    P.nlist = (int *)h->dalloc(sizeof(int) * (size_t)kNbr * c);
+    P.nlist = nullptr;
+    P.nbr = 0;
+    h->nlist_rows = 0;
     P.nnb = (int *)h->dalloc(sizeof(int) * c);
     P.slot_of = (int *)h->dalloc(sizeof(int) * c);
     P.xbuild = (double *)h->dalloc(sizeof(double) * 3 * c);
@@ -492,6 +513,7 @@ void put_particles(lbdem_domain_t h, const HostParticles &hp)
     h->dmax = 0.0;
     for (double v : hp.d) h->dmax = std::max(h->dmax, v);
     update_search(h);
+    ensure_lists(h);
     update_body_force(h, hp.d, hp.rho);
 }
 
@@ -529,7 +551,7 @@ void enqueue_step(lbdem_domain_t h)
         launch_cls(h, 6, [&] { launch_gather_fd<R>(h->desc(), C, s); });
         launch_cls(h, 8, [&] { launch_nlist(h->desc(), s); });
         for (int sub = 0; sub < h->phys.n_dem; ++sub) {
-            launch_cls(h, 9, [&] { launch_dem_force(h->desc(), std::is_same<R, float>::value, s); });
+            launch_cls(h, 9, [&] { launch_dem_force(h->desc(), s); });
             launch_cls(h, 10, [&] { launch_integrate(h->desc(), sub == h->phys.n_dem - 1, s); });
         }
         launch_cls(h, 11, [&] { sort_particles(h); });
@@ -732,6 +754,7 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
         alloc_particles(h, 64);
         h->pt.np = 0;
         update_search(h);
+        ensure_lists(h);
         rebuild(h);
         hip_check(hipStreamSynchronize(h->stream), "create sync");
         return LBDEM_OK;

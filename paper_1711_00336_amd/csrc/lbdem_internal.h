@@ -58,12 +58,14 @@ struct Bins {
 
 // Packed copy of what a DEM pair evaluation reads of a neighbour, one 64-byte
 // record per slot (FP32-deviation form only): one cache line per neighbour
-// instead of eleven scattered SoA loads. Positions stay FP64.
+// instead of eleven scattered SoA loads. Positions and diameters stay FP64;
+// mass, velocity and spin are rounded to FP32.
 struct alignas(64) DemRec {
     double x[3];
-    float d, m;
+    double d;                   // FP64: the overlap d_i/2 + d_j/2 - |x_j - x_i| cancels
+    float m;
     float u[3], w[3];
-    float pad[2];
+    float pad;
 };
 static_assert(sizeof(DemRec) == 64, "one 64-byte record");
 
@@ -84,9 +86,10 @@ struct Parts {
     double *Fdem, *Tdem;        // contact + lubrication force and torque of the substep
     double *ustart, *xstart;    // velocity / position at subcycle start
     double *Fam_id, *Fd_id, *Fpr_id, *Fc_id;  // last subcycle's forces by insertion index
-    // Verlet lists by insertion index: nlist[id*kNbr + t], nnb[id] entries,
+    // Verlet lists by insertion index: nlist[id*nbr + t], nnb[id] entries,
     // built from positions xbuild[3][cap] (by id); slot_of[id] = current slot
     int *nlist, *nnb, *slot_of;
+    int nbr;                    // list capacity per particle (sized from the density and reach)
     double *xbuild;
     int *need;                  // 1: rebuild the lists before the next DEM substep
     DemRec *pk, *pk2;           // packed DEM records by slot (+ permutation target), or null
@@ -112,11 +115,10 @@ enum : int {
     FLAG_SKIN = 2,              // moved more than the skin within a subcycle
     FLAG_NONFINITE = 4,
     FLAG_EPS = 8,               // eps_f <= 0
-    FLAG_NLIST = 16             // a particle has more than kNbr list neighbours
+    FLAG_NLIST = 16             // a particle has more list neighbours than the capacity nbr
 };
 
 constexpr int kTimingClasses = 12;  // kernel classes of lbdem_kernel_time
-constexpr int kNbr = 80;        // Verlet list capacity per particle
 
 constexpr int kBlock = 256;
 constexpr int kScanItems = 8;   // per thread in the block scan
@@ -141,7 +143,7 @@ void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials
                  hipStream_t s);
 int diag_blocks(const Desc &D);
 
-void launch_dem_force(const Desc &D, bool fp32_forces, hipStream_t s);  // pair math in FP32 or FP64
+void launch_dem_force(const Desc &D, hipStream_t s);
 void launch_nlist(const Desc &D, hipStream_t s);      // rebuild Verlet lists if flagged
 void launch_integrate(const Desc &D, int last_substep, hipStream_t s);
 void launch_bin_count(const Desc &D, hipStream_t s);

@@ -850,12 +850,17 @@ __global__ __launch_bounds__(256) void k_part_tile(Desc D, Cells<R> C, int recor
 // ---------------------------------------------------------------------------
 // a8: DEM (Sec. 3.1.1) + lubrication (Sec. 3.1.3) forces of one substep.
 // ---------------------------------------------------------------------------
-// Pair and wall forces are evaluated in the compute type T: double for the
-// FP64 path, float in the FP32-deviation form (positions, their differences
-// and the integration stay FP64 in both).
+// Pair and wall forces are evaluated in the compute type T (double in both
+// storage forms: FP32 pair arithmetic was measured to cost ~5e-5 relative
+// error per step in dense, lubrication-dominated packings). Positions,
+// radii, the centre distance and the overlap (or gap) are FP64 whatever T
+// is: the overlap is a small difference of O(1) lengths. In the
+// FP32-deviation form the neighbour velocities, spins and masses come from
+// the packed records, rounded to FP32.
 template <typename T> struct PV {
     T r, m, d;
     double x[3];
+    double rr;                  // radius, FP64
     T u[3], w[3];
 };
 
@@ -923,15 +928,15 @@ __device__ __forceinline__ void lubrication(const Phys &p, T h, T dm, T mij, con
 }
 
 template <typename T>
-__device__ __forceinline__ void pair_interaction(const Phys &p, const PV<T> &pi, const PV<T> &pj, const T dx[3],
+__device__ __forceinline__ void pair_interaction(const Phys &p, const PV<T> &pi, const PV<T> &pj, const double dx[3],
                                                  T F[3], T Tq[3])
 {
-    const T dist2 = dot3(dx, dx);
-    const T reach = pi.r + pj.r + (p.use_lub ? (T)fmax(p.h_c, 0.0) : (T)0);
+    const double dist2 = dot3(dx, dx);
+    const double reach = pi.rr + pj.rr + (p.use_lub ? fmax(p.h_c, 0.0) : 0.0);
     if (dist2 >= reach * reach) return;
-    const T dist = sqrt(dist2);
-    const T n[3] = {dx[0] / dist, dx[1] / dist, dx[2] / dist};
-    const T delta = pi.r + pj.r - dist;
+    const double dist = sqrt(dist2);
+    const T n[3] = {(T)(dx[0] / dist), (T)(dx[1] / dist), (T)(dx[2] / dist)};
+    const T delta = (T)(pi.rr + pj.rr - dist);
     const T mij = pi.m * pj.m / (pi.m + pj.m);
     if (delta > (T)0) {
         T s[3], ur[3];
@@ -955,10 +960,10 @@ __device__ __forceinline__ void wall_interaction(const Phys &p, const Geo &g, co
     for (int a = 0; a < 3; ++a) {
         if (g.per[a]) continue;
         for (int side = 0; side < 2; ++side) {
-            const T dist = (T)(side == 0 ? pi.x[a] : (double)g.n[a] - pi.x[a]);
+            const double dist = side == 0 ? pi.x[a] : (double)g.n[a] - pi.x[a];
             T n[3] = {(T)0, (T)0, (T)0};
             n[a] = side == 0 ? (T)-1 : (T)1;
-            const T delta = pi.r - dist;
+            const T delta = (T)(pi.rr - dist);
             if (delta > (T)0) {
                 T s[3], ur[3];
 #pragma unroll
@@ -979,6 +984,7 @@ template <typename T> __device__ __forceinline__ void load_pv(const Parts &P, in
     const double d = P.d[i];
     v.d = (T)d;
     v.r = (T)(0.5 * d);
+    v.rr = 0.5 * d;
     v.m = (T)(P.rho[i] * sphere_volume(d));
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -998,37 +1004,39 @@ __device__ __forceinline__ void store_rec(DemRec *pk, int64_t i, const double x[
         r.u[a] = (float)u[a];
         r.w[a] = (float)w[a];
     }
-    r.d = (float)d;
+    r.d = d;
     r.m = (float)(rho * sphere_volume(d));
-    r.pad[0] = r.pad[1] = 0.0f;
+    r.pad = 0.0f;
     const uint4 *src = reinterpret_cast<const uint4 *>(&r);
     uint4 *dst = reinterpret_cast<uint4 *>(pk + i);
 #pragma unroll
     for (int k = 0; k < 4; ++k) dst[k] = src[k];
 }
 
-// the same values load_pv<float> gives, from one 64-byte record
-__device__ __forceinline__ void load_rec(const DemRec *pk, int64_t i, PV<float> &v)
+// a particle's DEM view from its 64-byte record: FP64 position and
+// diameter, velocity, spin and mass as stored (FP32)
+template <typename T> __device__ __forceinline__ void load_rec(const DemRec *pk, int64_t i, PV<T> &v)
 {
     const uint4 *src = reinterpret_cast<const uint4 *>(pk + i);
     DemRec r;
     uint4 *dst = reinterpret_cast<uint4 *>(&r);
 #pragma unroll
     for (int k = 0; k < 4; ++k) dst[k] = src[k];
-    v.d = r.d;
-    v.r = 0.5f * r.d;
-    v.m = r.m;
+    v.d = (T)r.d;
+    v.r = (T)(0.5 * r.d);
+    v.rr = 0.5 * r.d;
+    v.m = (T)r.m;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         v.x[a] = r.x[a];
-        v.u[a] = r.u[a];
-        v.w[a] = r.w[a];
+        v.u[a] = (T)r.u[a];
+        v.w[a] = (T)r.w[a];
     }
 }
 
-template <typename T> __device__ __forceinline__ void load_particle(const Parts &P, int64_t i, PV<T> &v)
+template <typename T, bool REC> __device__ __forceinline__ void load_particle(const Parts &P, int64_t i, PV<T> &v)
 {
-    if constexpr (sizeof(T) == 4) load_rec(P.pk, i, v);
+    if constexpr (REC) load_rec(P.pk, i, v);
     else load_pv(P, i, v);
 }
 
@@ -1070,7 +1078,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
     const int mz = axis_range(b2, R, D.g.n[2], D.g.per[2], cz, 2 * kMaxR + 1);
     const bool run = mx >= 1 && cx[mx - 1] - cx[0] == mx - 1;
     const int nrun = run ? 1 : mx;
-    int *L = P.nlist + (int64_t)me * kNbr;
+    int *L = P.nlist + (int64_t)me * P.nbr;
     int m = 0;
     for (int c2 = 0; c2 < mz; ++c2)
         for (int c1 = 0; c1 < my; ++c1)
@@ -1084,7 +1092,7 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
                     min_image(D.g, dx);
                     const double reach = ri + 0.5 * P.d[j] + gap;
                     if (dot3(dx, dx) >= reach * reach) continue;
-                    if (m < kNbr) {
+                    if (m < P.nbr) {
                         // insertion by ascending insertion index
                         const int v = P.id[j];
                         int t = m - 1;
@@ -1097,9 +1105,9 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
                     ++m;
                 }
             }
-    if (m > kNbr) {
+    if (m > P.nbr) {
         atomicOr(D.flags, FLAG_NLIST);
-        m = kNbr;
+        m = P.nbr;
     }
     P.nnb[me] = m;
     P.xbuild[me] = xi0;
@@ -1108,12 +1116,11 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
 }
 
 // contact + lubrication force and torque on every particle from its list.
-// The list is walked in chunks of entries (4 in FP32, 2 in FP64, to bound
-// register use) whose indices, slots and particle data are requested
-// together, so their memory latencies overlap; pairs are still summed in
-// list order.
+// The list is walked in chunks of two entries whose indices, slots and
+// particle data are requested together, so their memory latencies overlap;
+// pairs are still summed in list order.
 
-template <typename T>
+template <typename T, bool REC>
 __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
 {
     const Parts &P = D.pt;
@@ -1121,27 +1128,26 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
     if (i == 0) *P.need = 0;  // lists are current for this subcycle
     if (i >= P.np) return;
     PV<T> pi;
-    load_particle(P, i, pi);
+    load_particle<T, REC>(P, i, pi);
     T F[3] = {(T)0, (T)0, (T)0}, Tq[3] = {(T)0, (T)0, (T)0};
-    const T gap = D.p.use_lub ? (T)fmax(D.p.h_c, 0.0) : (T)0;
+    const double gap = D.p.use_lub ? fmax(D.p.h_c, 0.0) : 0.0;
     const int me = P.id[i];
     const int n = P.nnb[me];
-    const int *L = P.nlist + (int64_t)me * kNbr;
-    constexpr int kChunk = sizeof(T) == 4 ? 4 : 2;
+    const int *L = P.nlist + (int64_t)me * P.nbr;
+    constexpr int kChunk = 2;
     for (int t0 = 0; t0 < n; t0 += kChunk) {
         int js[kChunk];
 #pragma unroll
         for (int c = 0; c < kChunk; ++c) js[c] = t0 + c < n ? P.slot_of[L[t0 + c]] : (int)i;
         PV<T> pj[kChunk];
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) load_particle(P, js[c], pj[c]);
+        for (int c = 0; c < kChunk; ++c) load_particle<T, REC>(P, js[c], pj[c]);
 #pragma unroll
         for (int c = 0; c < kChunk; ++c) {
             if (t0 + c >= n) break;
-            double dxd[3] = {pj[c].x[0] - pi.x[0], pj[c].x[1] - pi.x[1], pj[c].x[2] - pi.x[2]};
-            min_image(D.g, dxd);
-            const T dx[3] = {(T)dxd[0], (T)dxd[1], (T)dxd[2]};
-            const T reach = pi.r + pj[c].r + gap;
+            double dx[3] = {pj[c].x[0] - pi.x[0], pj[c].x[1] - pi.x[1], pj[c].x[2] - pi.x[2]};
+            min_image(D.g, dx);
+            const double reach = pi.rr + pj[c].rr + gap;
             if (dot3(dx, dx) >= reach * reach) continue;
             pair_interaction(D.p, pi, pj[c], dx, F, Tq);
         }
@@ -1645,11 +1651,11 @@ void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials
     hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, (const double *)partials, nblk, out);
 }
 
-void launch_dem_force(const Desc &D, bool fp32, hipStream_t s)
+void launch_dem_force(const Desc &D, hipStream_t s)
 {
     if (D.pt.np == 0) return;
-    if (fp32) hipLaunchKernelGGL(k_dem_force<float>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
-    else hipLaunchKernelGGL(k_dem_force<double>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+    if (D.pt.pk) hipLaunchKernelGGL((k_dem_force<double, true>), dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+    else hipLaunchKernelGGL((k_dem_force<double, false>), dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
 }
 void launch_nlist(const Desc &D, hipStream_t s)
 {

@@ -70,12 +70,17 @@ lbdem_status sfail(lbdem_status st, const std::string &m)
 }
 
 // device bytes of one domain: two PDF buffers and 30 field components per
-// cell in the storage precision, bins, and per-particle state incl. lists
-size_t footprint_of(const lbdem_params &p, int64_t np)
+// cell in the storage precision, bins, per-particle state, and the Verlet
+// lists (capacity twice the mean neighbour count within d_max + h_c + 0.4,
+// plus 24 entries, as the domain sizes them)
+size_t footprint_of(const lbdem_params &p, int64_t np, double dmax)
 {
     const size_t nc = (size_t)p.n[0] * p.n[1] * p.n[2];
     const size_t rs = p.precision == LBDEM_FP64 ? 8 : 4;
-    return nc * (rs * (2 * 19 + 30) + 12) + (size_t)std::max<int64_t>(np, 64) * 1400 + (32u << 20);
+    const double reach = dmax + (p.use_lub ? std::max(p.h_c, 0.0) : 0.0) + 0.4;
+    const double nbr = 2.0 * (double)np / (double)nc * (4.0 / 3.0) * M_PI * reach * reach * reach + 28.0;
+    const size_t per_particle = 1100 + 4 * (size_t)std::max(32.0, nbr);
+    return nc * (rs * (2 * 19 + 30) + 12) + (size_t)std::max<int64_t>(np, 64) * per_particle + (32u << 20);
 }
 
 void finish(lbdem_server_t s, uint64_t t, Req &r, lbdem_status st)
@@ -222,7 +227,9 @@ lbdem_status lbdem_server_submit(lbdem_server_t s, const lbdem_request *r, uint6
     q.prm = r->params;
     q.steps = r->steps;
     q.avg_from = std::max<int64_t>(0, std::min<int64_t>(r->avg_from, r->steps - 1));
-    q.footprint = footprint_of(r->params, r->np);
+    double dmax = 0.0;
+    for (int64_t i = 0; i < r->np; ++i) dmax = std::max(dmax, r->d[i]);
+    q.footprint = footprint_of(r->params, r->np, dmax);
     if (q.footprint > s->budget) return sfail(LBDEM_E_INVALID, "request exceeds the server's HBM budget");
     const int64_t n = r->np;
     q.x.assign(r->x, r->x + 3 * n);

@@ -232,7 +232,7 @@ def build_relax(force: bool = False) -> str:
             os.path.getmtime(_RELAX_LIB) < os.path.getmtime(_RELAX_SRC):
         os.makedirs(os.path.dirname(_RELAX_LIB), exist_ok=True)
         tmp = _RELAX_LIB + ".tmp%d" % os.getpid()
-        subprocess.run(["gcc", "-O2", "-std=gnu11", "-shared", "-fPIC", "-o", tmp, _RELAX_SRC, "-lm"],
+        subprocess.run(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-shared", "-fPIC", "-o", tmp, _RELAX_SRC, "-lm"],
                        check=True)
         os.replace(tmp, _RELAX_LIB)
     return _RELAX_LIB
@@ -250,21 +250,32 @@ def _relax_lib():
     return _relax_fn
 
 
-def _relax(pos, r, box, periodic, tol, max_it=4000):
+def _relax(pos, r, box, periodic, tol, max_it=4000, progress=None):
     """Remove overlaps by equal and opposite half-overlap pushes (geometry
     only, Gauss-Seidel sweeps over a cell list in inputs_relax.c), until the
-    largest overlap is below tol. Returns (positions, converged)."""
+    largest overlap is below tol. Returns (positions, converged). The sweeps
+    run in chunks (each sweep rebuilds its cell list, so chunking does not
+    change the result); progress(sweeps_done) is called after each chunk."""
     pos = np.ascontiguousarray(pos, np.float64).copy()
     r = np.ascontiguousarray(r, np.float64)
     boxa = np.asarray(box, np.float64)
     per = np.asarray([1 if p else 0 for p in periodic], np.int32)
     dp = ctypes.POINTER(ctypes.c_double)
-    it = _relax_lib()(len(r), pos.ctypes.data_as(dp), r.ctypes.data_as(dp), boxa.ctypes.data_as(dp),
-                      per.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(tol), int(max_it))
-    return pos, it >= 0
+    done = 0
+    chunk = 25 if progress else max_it
+    while done < max_it:
+        k = min(chunk, max_it - done)
+        it = _relax_lib()(len(r), pos.ctypes.data_as(dp), r.ctypes.data_as(dp), boxa.ctypes.data_as(dp),
+                          per.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(tol), int(k))
+        if it >= 0:
+            return pos, True
+        done += k
+        if progress:
+            progress(done)
+    return pos, False
 
 
-def place_spheres(seed, box, periodic, diam, max_rounds=400, relax_tol=1e-3):
+def place_spheres(seed, box, periodic, diam, max_rounds=400, relax_tol=1e-3, progress=None):
     """Non-overlapping uniform random spheres.
 
     First a parallel random sequential addition: particle i is redrawn while
@@ -282,7 +293,7 @@ def place_spheres(seed, box, periodic, diam, max_rounds=400, relax_tol=1e-3):
         return np.zeros((0, 3))
     frac = float((np.pi / 6.0 * diam ** 3).sum() / (box[0] * box[1] * box[2]))
     if frac > 0.25:
-        return _place_dense(seed, box, periodic, diam, frac, relax_tol)
+        return _place_dense(seed, box, periodic, diam, frac, relax_tol, progress)
     r = 0.5 * diam
     dmax = float(diam.max())
     pos = _draw_positions(seed, 0, 0, n, box, periodic, r)
@@ -308,7 +319,7 @@ def place_spheres(seed, box, periodic, diam, max_rounds=400, relax_tol=1e-3):
     raise RuntimeError("sphere placement did not converge")
 
 
-def _place_dense(seed, box, periodic, diam, frac, relax_tol):
+def _place_dense(seed, box, periodic, diam, frac, relax_tol, progress=None):
     """Dense packings (beyond the random-sequential-addition limit): uniform
     random centres, then geometric overlap removal with tolerances tightened
     in stages down to relax_tol * d_min (random placement followed by overlap
@@ -317,7 +328,8 @@ def _place_dense(seed, box, periodic, diam, frac, relax_tol):
     pos = _draw_positions(seed, 0, 0, len(diam), box, periodic, r)
     dmin = float(diam.min())
     for tol in (0.05 * dmin, 0.01 * dmin, relax_tol * dmin):
-        pos, ok = _relax(pos, r, box, periodic, tol, max_it=100000)
+        cb = (lambda k, t=tol: progress(f"overlap removal to {t:.1e}: {k} sweeps")) if progress else None
+        pos, ok = _relax(pos, r, box, periodic, tol, max_it=100000, progress=cb)
         if not ok:
             raise RuntimeError("dense sphere placement did not converge")
     return pos
@@ -349,10 +361,10 @@ def draw_diameters(seed, n_or_eps, ncells, d_lo, d_hi):
     return d_lo + (d_hi - d_lo) * uniform(seed, _S_DIAM, 0, n)
 
 
-def make_particles(seed, params: Params, n_or_eps, d_lo, d_hi, rho_ratio):
+def make_particles(seed, params: Params, n_or_eps, d_lo, d_hi, rho_ratio, progress=None):
     nc = params.n[0] * params.n[1] * params.n[2]
     d = draw_diameters(seed, n_or_eps, nc, d_lo, d_hi)
-    pos = place_spheres(seed, params.n, params.periodic, d)
+    pos = place_spheres(seed, params.n, params.periodic, d, progress=progress)
     n = len(d)
     rp = np.full(n, float(rho_ratio) * params.rho_f)
     return Particles(pos, np.zeros((n, 3)), np.zeros((n, 3)), d, rp)
@@ -386,13 +398,13 @@ def case_dilute_periodic(seed=0, n=128, eps_p=0.05, d=0.8, precision="fp32dev"):
 
 
 def case_dense_walled(seed=0, n=(256, 256, 512), eps_p=0.4, precision="fp32dev",
-                      n_dem=10, n_int=10):
+                      n_dem=10, n_int=10, progress=None):
     """Dense suspension: walls in z, d ~ U[0.9, 1.1], solid fraction 0.4,
     density ratio 2.5, restitution 0.9, lubrication with cut-off 1.0."""
     p = Params(n=tuple(n), periodic=(1, 1, 0), tau=0.7, gravity=(0.0, 0.0, -1e-5),
                body_force_auto=0, e_n=0.9, mu_c=0.25, T_c=0.0, h_c=1.0,
                n_int=n_int, n_dem=n_dem, precision=precision)
-    parts = make_particles(seed, p, float(eps_p), 0.9, 1.1, 2.5)
+    parts = make_particles(seed, p, float(eps_p), 0.9, 1.1, 2.5, progress=progress)
     return Case(f"dense-{n[0]}x{n[1]}x{n[2]}-eps{eps_p}", p, parts, seed)
 
 

@@ -3,11 +3,18 @@
  * Not part of the method: overlapping pairs are pushed apart along their
  * centre line by half the overlap each (Gauss-Seidel sweeps over a cell
  * list), walls clamp centres to [r, L - r], periodic axes wrap.
+ *
+ * Cells are visited in 27 colour classes (cell coordinates mod 3); cells of
+ * one class have disjoint 3x3x3 neighbourhoods, so a class is processed in
+ * parallel (OpenMP) and the result does not depend on the thread count.
  */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 static double wrapd(double x, double L)
 {
@@ -15,6 +22,61 @@ static double wrapd(double x, double L)
     else if (x < 0.0) x -= L * floor(x / L);
     if (x >= L) x = 0.0;
     return x;
+}
+
+static void relax_cell(int64_t c, int cx, int cy, int cz, const int nb[3], const int64_t *start,
+                       const int64_t *order, double *pos, const double *r, const double *box, const int32_t *per,
+                       double tol, double *maxov_out)
+{
+    double maxov = *maxov_out;
+    for (int64_t t = start[c]; t < start[c + 1]; ++t) {
+        const int64_t i = order[t];
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int q[3] = {cx + dx, cy + dy, cz + dz}, ok = 1;
+                    for (int a = 0; a < 3; ++a) {
+                        if (q[a] < 0 || q[a] >= nb[a]) {
+                            if (per[a]) q[a] = (q[a] + nb[a]) % nb[a];
+                            else ok = 0;
+                        }
+                    }
+                    if (!ok) continue;
+                    /* with fewer than 3 cells on an axis a neighbour cell repeats;
+                     * visit each distinct cell once */
+                    int dup = 0;
+                    for (int a = 0; a < 3 && !dup; ++a) {
+                        const int d = a == 0 ? dx : (a == 1 ? dy : dz);
+                        if (nb[a] == 1 && d != 0) dup = 1;
+                        if (nb[a] == 2 && d == 1) dup = 1;
+                    }
+                    if (dup) continue;
+                    const int64_t c2 = q[0] + (int64_t)nb[0] * (q[1] + (int64_t)nb[1] * q[2]);
+                    for (int64_t u = start[c2]; u < start[c2 + 1]; ++u) {
+                        const int64_t j = order[u];
+                        if (j <= i) continue;
+                        double d[3], d2 = 0.0;
+                        for (int a = 0; a < 3; ++a) {
+                            d[a] = pos[3 * j + a] - pos[3 * i + a];
+                            if (per[a]) d[a] -= box[a] * nearbyint(d[a] / box[a]);
+                            d2 += d[a] * d[a];
+                        }
+                        const double s = r[i] + r[j];
+                        if (d2 >= s * s) continue;
+                        const double dist = sqrt(d2);
+                        const double ov = s - dist;
+                        if (ov > maxov) maxov = ov;
+                        const double push = 0.5 * ov + 0.5 * tol;
+                        double nrm[3];
+                        for (int a = 0; a < 3; ++a) nrm[a] = dist > 1e-12 ? d[a] / dist : (a == 0 ? 1.0 : 0.0);
+                        for (int a = 0; a < 3; ++a) {
+                            pos[3 * i + a] -= push * nrm[a];
+                            pos[3 * j + a] += push * nrm[a];
+                        }
+                    }
+                }
+    }
+    *maxov_out = maxov;
 }
 
 /* returns the number of sweeps used, or -1 if max_sweeps was reached */
@@ -30,9 +92,13 @@ int lbdem_inputs_relax(int64_t n, double *pos, const double *r, const double *bo
     for (int a = 0; a < 3; ++a) {
         nb[a] = (int)floor(box[a] / (2.0 * rmax));
         if (nb[a] < 1) nb[a] = 1;
+        /* periodic axes: a multiple of 3 cells, so colour classes stay apart
+         * across the wrap (cells only grow) */
+        if (per[a] && nb[a] >= 3) nb[a] -= nb[a] % 3;
         cs[a] = box[a] / nb[a];
         ncell *= nb[a];
     }
+    const int serial = nb[0] < 3 || nb[1] < 3 || nb[2] < 3;
     int64_t *start = malloc(sizeof(int64_t) * (size_t)(ncell + 1));
     int64_t *cnt = malloc(sizeof(int64_t) * (size_t)ncell);
     int64_t *order = malloc(sizeof(int64_t) * (size_t)n);
@@ -55,54 +121,16 @@ int lbdem_inputs_relax(int64_t n, double *pos, const double *r, const double *bo
         memset(cnt, 0, sizeof(int64_t) * (size_t)ncell);
         for (int64_t i = 0; i < n; ++i) order[start[cell[i]] + cnt[cell[i]]++] = i;
         double maxov = 0.0;
-        for (int64_t c = 0; c < ncell; ++c) {
-            const int cx = (int)(c % nb[0]), cy = (int)((c / nb[0]) % nb[1]), cz = (int)(c / ((int64_t)nb[0] * nb[1]));
-            for (int64_t t = start[c]; t < start[c + 1]; ++t) {
-                const int64_t i = order[t];
-                for (int dz = -1; dz <= 1; ++dz)
-                    for (int dy = -1; dy <= 1; ++dy)
-                        for (int dx = -1; dx <= 1; ++dx) {
-                            int q[3] = {cx + dx, cy + dy, cz + dz}, ok = 1;
-                            for (int a = 0; a < 3; ++a) {
-                                if (q[a] < 0 || q[a] >= nb[a]) {
-                                    if (per[a]) q[a] = (q[a] + nb[a]) % nb[a];
-                                    else ok = 0;
-                                }
-                            }
-                            if (!ok) continue;
-                            /* with fewer than 3 cells on an axis a neighbour cell repeats;
-                             * visit each distinct cell once */
-                            int dup = 0;
-                            for (int a = 0; a < 3 && !dup; ++a) {
-                                const int d = a == 0 ? dx : (a == 1 ? dy : dz);
-                                if (nb[a] == 1 && d != 0) dup = 1;
-                                if (nb[a] == 2 && d == 1) dup = 1;
-                            }
-                            if (dup) continue;
-                            const int64_t c2 = q[0] + (int64_t)nb[0] * (q[1] + (int64_t)nb[1] * q[2]);
-                            for (int64_t u = start[c2]; u < start[c2 + 1]; ++u) {
-                                const int64_t j = order[u];
-                                if (j <= i) continue;
-                                double d[3], d2 = 0.0;
-                                for (int a = 0; a < 3; ++a) {
-                                    d[a] = pos[3 * j + a] - pos[3 * i + a];
-                                    if (per[a]) d[a] -= box[a] * nearbyint(d[a] / box[a]);
-                                    d2 += d[a] * d[a];
-                                }
-                                const double s = r[i] + r[j];
-                                if (d2 >= s * s) continue;
-                                const double dist = sqrt(d2);
-                                const double ov = s - dist;
-                                if (ov > maxov) maxov = ov;
-                                const double push = 0.5 * ov + 0.5 * tol;
-                                double nrm[3];
-                                for (int a = 0; a < 3; ++a) nrm[a] = dist > 1e-12 ? d[a] / dist : (a == 0 ? 1.0 : 0.0);
-                                for (int a = 0; a < 3; ++a) {
-                                    pos[3 * i + a] -= push * nrm[a];
-                                    pos[3 * j + a] += push * nrm[a];
-                                }
-                            }
-                        }
+        for (int color = 0; color < 27; ++color) {
+            const int ox = color % 3, oy = (color / 3) % 3, oz = color / 9;
+            const int mx = (nb[0] - ox + 2) / 3, my = (nb[1] - oy + 2) / 3, mz = (nb[2] - oz + 2) / 3;
+            const int64_t mcells = (int64_t)mx * my * mz;
+#pragma omp parallel for schedule(dynamic, 16) reduction(max : maxov) if (!serial)
+            for (int64_t m = 0; m < mcells; ++m) {
+                const int cx = ox + 3 * (int)(m % mx), cy = oy + 3 * (int)((m / mx) % my),
+                          cz = oz + 3 * (int)(m / ((int64_t)mx * my));
+                const int64_t c = cx + (int64_t)nb[0] * (cy + (int64_t)nb[1] * cz);
+                relax_cell(c, cx, cy, cz, nb, start, order, pos, r, box, per, tol, &maxov);
             }
         }
         for (int64_t i = 0; i < n; ++i)

@@ -123,6 +123,13 @@ def test_gather_variants_bitwise_equal_and_match_oracle(L, eps):
             dom.lbdem_set_gather_variant(4)
 
 
+def test_parity_crowded_small_spheres_list_capacity(L):
+    """Small spheres at solid fraction 0.5 (d = 0.6, about 76 neighbours
+    within the list reach): the list capacity follows the density."""
+    case = I.case_settling(11, 16, 0.5, 0.6, 1.5, precision="fp64", tau=I.SWEEP_TAU)
+    _one_step_parity(L, case, warm=1, nsteps=2)
+
+
 def test_parity_degenerate_thin_periodic_axis(L):
     """A periodic axis of 2 cells: kernel stencils and neighbour bins wrap onto
     themselves."""
