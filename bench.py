@@ -42,8 +42,8 @@ def _gen_batch_domain(args):
 
 def _gen_request(args):
     from paper_1711_00336_amd import inputs as I
-    seed, i = args
-    edge, eps, d, rr, steps = I.serving_request_draw(seed, i)
+    seed, i, edge_hi, steps_hi = args
+    edge, eps, d, rr, steps = I.serving_request_draw(seed, i, edge_hi=edge_hi, steps_hi=steps_hi)
     c = I.case_settling(seed * 1000003 + i, edge, eps, d, rr, precision="fp32dev", tau=I.SWEEP_TAU)
     return c, steps
 
@@ -315,7 +315,8 @@ def bench_serve(args):
     lines = []
     for rate in rates:
         seed = args.seed * 7 + int(rate)
-        gen = _pool_map(_gen_request, [(seed, i) for i in range(R)], f"requests (rate {rate:g}/s)")
+        gen = _pool_map(_gen_request, [(seed, i, args.edge_hi, args.steps_hi) for i in range(R)],
+                        f"requests (rate {rate:g}/s)")
         arrivals = I.poisson_arrivals(seed, rate, R)
         free, _total = torch.cuda.mem_get_info()
         budget = int(0.9 * free)
@@ -377,7 +378,8 @@ def bench_serve(args):
             "metric": METRIC, "mode": "serve", "rate_per_s": rate, "requests": R, "failed": len(bad),
             "value": round(R / span, 4), "unit": "solves/s", "higher_is_better": True, "n_gpus": 1,
             "data": "synthetic",
-            "config": {"workload": "settling-requests-edge24-160", "hbm_budget_gb": round(budget / 1e9, 1),
+            "config": {"workload": f"settling-requests-edge24-{args.edge_hi}-steps200-{args.steps_hi}",
+                       "hbm_budget_gb": round(budget / 1e9, 1),
                        "slots": args.slots, "chunk_steps": args.chunk,
                        "mean_cells": int(cells.mean()), "mean_steps": float(steps.mean())},
             "p50_s": round(float(np.percentile(lat, 50)), 3), "p99_s": round(float(np.percentile(lat, 99)), 3),
@@ -410,6 +412,8 @@ def main():
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--chunk", type=int, default=50)
     ap.add_argument("--plain-sample", type=int, default=100)
+    ap.add_argument("--edge-hi", type=int, default=160)
+    ap.add_argument("--steps-hi", type=int, default=5000)
     ap.add_argument("--no-k10", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     args = ap.parse_args()
