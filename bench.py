@@ -442,6 +442,8 @@ def main():
     dom = lbdem.Domain(case.params, stream=stream.cuda_stream)
     dom.add(case.particles)
     nc = dom.nc
+    variant = dom.lbdem_autotune()
+    print(f"[bench] autotuned gather variant {variant}", file=sys.stderr, flush=True)
 
     dom.lbdem_step(args.warmup)
     dom.lbdem_sync()
@@ -522,7 +524,7 @@ def main():
         "config": {"workload": case.name, "cells": int(nc), "particles": int(case.particles.n),
                    "n_int": case.params.n_int, "n_dem": case.params.n_dem,
                    "pdf_storage": "f32 deviation" if case.params.precision == "fp32dev" else "f64 deviation",
-                   "particle_integration": "f64", "tau": case.params.tau},
+                   "particle_integration": "f64", "tau": case.params.tau, "gather_variant": variant},
         "roofline": roofline,
         "roofline_stream_collide": roof_k10,
         "cpu_baseline": cpu,

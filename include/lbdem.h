@@ -209,7 +209,8 @@ lbdem_status lbdem_autotune(lbdem_domain_t h, int32_t *gather_variant);
  * the volume fraction and the spread forces): -1 automatic by particle
  * density (the default), 0 LDS tiles of 16x4x8 cells, 1 LDS tiles of
  * 16x4x4, 2 LDS tiles of 8x4x4, 3 one thread per cell reading the particle
- * bins from global memory. E_INVALID for other values. */
+ * bins from global memory (and the drag pass one thread per particle),
+ * 4 LDS tiles of 16x4x16. E_INVALID for other values. */
 lbdem_status lbdem_set_gather_variant(lbdem_domain_t h, int32_t variant);
 
 /* ---- Batching: many independent domains (e.g. a parameter sweep of the

@@ -97,7 +97,7 @@ struct Parts {
 
 // launch choices picked per domain (autotuner); -1 = heuristic default
 struct Tune {
-    int gather;                 // -1 by density; 0/1/2 LDS tiles 16x4x8, 16x4x4, 8x4x4; 3 per cell
+    int gather;                 // -1 by density; 0/1/2/4 LDS tiles 16x4x8, 16x4x4, 8x4x4, 16x4x16; 3 per cell
 };
 
 struct Desc {
@@ -133,7 +133,7 @@ template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, in
 template <typename R> void launch_gather_fd(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_eps_am(const Desc &D, const Cells<R> &C, hipStream_t s);
-constexpr int kGatherVariants = 4;
+constexpr int kGatherVariants = 5;
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s);
 template <typename R> void launch_to_double(const R *src, double *dst, int64_t n, hipStream_t s);

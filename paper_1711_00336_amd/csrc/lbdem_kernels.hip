@@ -355,24 +355,26 @@ __device__ __forceinline__ double stencil_w(const Parts &P, int64_t p, int axis,
     return (o >= -1 && o <= 1) ? sw[(o + 1) * P.cap] : 0.0;
 }
 
-template <int NV, typename F>
+// weights and values in the storage precision R, products accumulated in
+// FP64 (the same arithmetic as the LDS tiles, so all variants agree)
+template <typename R, int NV, typename F>
 __device__ __forceinline__ void gather_range(const Desc &D, int i, int j, int k, int p0, int p1, const F &val,
                                              double *s)
 {
     for (int p = p0; p < p1; ++p) {
-        const double wx = stencil_w(D.pt, p, 0, i, D.g.n[0], D.g.per[0]);
-        const double wy = stencil_w(D.pt, p, 1, j, D.g.n[1], D.g.per[1]);
-        const double wz = stencil_w(D.pt, p, 2, k, D.g.n[2], D.g.per[2]);
-        const double w = wx * wy * wz;
-        if (w == 0.0) continue;
+        const R wx = (R)stencil_w(D.pt, p, 0, i, D.g.n[0], D.g.per[0]);
+        const R wy = (R)stencil_w(D.pt, p, 1, j, D.g.n[1], D.g.per[1]);
+        const R wz = (R)stencil_w(D.pt, p, 2, k, D.g.n[2], D.g.per[2]);
+        const R w = wx * wy * wz;
+        if (w == (R)0) continue;
         double v[NV];
         val(p, v);
 #pragma unroll
-        for (int q = 0; q < NV; ++q) s[q] += w * v[q];
+        for (int q = 0; q < NV; ++q) s[q] += (double)w * (double)(R)v[q];
     }
 }
 
-template <int NV, typename F>
+template <typename R, int NV, typename F>
 __device__ __forceinline__ void gather_cell(const Desc &D, int i, int j, int k, const F &val, double *s)
 {
     int cx[3], cy[3], cz[3];
@@ -387,11 +389,11 @@ __device__ __forceinline__ void gather_cell(const Desc &D, int i, int j, int k, 
         for (int b = 0; b < my; ++b) {
             if (run) {
                 const int64_t b0 = cidx(D.g, cx[0], cy[b], cz[a]);
-                gather_range<NV>(D, i, j, k, D.b.start[b0], D.b.start[b0 + 3], val, s);
+                gather_range<R, NV>(D, i, j, k, D.b.start[b0], D.b.start[b0 + 3], val, s);
             } else {
                 for (int c = 0; c < mx; ++c) {
                     const int64_t bin = cidx(D.g, cx[c], cy[b], cz[a]);
-                    gather_range<NV>(D, i, j, k, D.b.start[bin], D.b.start[bin + 1], val, s);
+                    gather_range<R, NV>(D, i, j, k, D.b.start[bin], D.b.start[bin + 1], val, s);
                 }
             }
         }
@@ -485,8 +487,10 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
     static_assert(NT % 64 == 0, "whole wavefronts");
     __shared__ int hoff[NHB + 1];
     __shared__ int wsum[NW];
-    __shared__ double sw_l[9][KMAX];
-    __shared__ double sv_l[NV][KMAX];
+    // staged weights and values in the storage precision R (halves LDS in the
+    // FP32 form); products are accumulated in FP64
+    __shared__ R sw_l[9][KMAX];
+    __shared__ R sv_l[NV][KMAX];
 
     const int tid = threadIdx.x;
     const int n0 = D.g.n[0], n1 = D.g.n[1], n2 = D.g.n[2];
@@ -556,11 +560,11 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
             if (kk >= KMAX) break;
             const int p = src[t] + q;
 #pragma unroll
-            for (int u = 0; u < 9; ++u) sw_l[u][kk] = P.sw[u * P.cap + p];
+            for (int u = 0; u < 9; ++u) sw_l[u][kk] = (R)P.sw[u * P.cap + p];
             double v[NV];
             gather_value<MODE>(P, p, v);
 #pragma unroll
-            for (int u = 0; u < NV; ++u) sv_l[u][kk] = v[u];
+            for (int u = 0; u < NV; ++u) sv_l[u][kk] = (R)v[u];
         }
         run += cnt[t];
     }
@@ -576,7 +580,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
 #pragma unroll
         for (int c = 0; c < CZ; ++c) {
             if (kb + c >= n2) break;
-            gather_cell<NV>(D, i, j, kb + c, [&](int p, double *v) { gather_value<MODE>(D.pt, p, v); }, s[c]);
+            gather_cell<R, NV>(D, i, j, kb + c, [&](int p, double *v) { gather_value<MODE>(D.pt, p, v); }, s[c]);
             gather_store<R, MODE>(D, C, cidx(D.g, i, j, kb + c), s[c]);
         }
         return;
@@ -598,17 +602,17 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
             const int k0 = hoff[hb0], k1 = hoff[hb0 + 1], k2 = hoff[hb0 + 2], k3 = hoff[hb0 + 3];
             for (int kk = k0; kk < k3; ++kk) {
                 const int sx = kk < k1 ? 2 : (kk < k2 ? 1 : 0);
-                const double wxy = sw_l[sx][kk] * sw_l[3 + 2 - dy][kk];
-                double v[NV];
+                const R wxy = sw_l[sx][kk] * sw_l[3 + 2 - dy][kk];
+                R v[NV];
 #pragma unroll
                 for (int t = 0; t < NV; ++t) v[t] = sv_l[t][kk];
 #pragma unroll
                 for (int c = 0; c < CZ; ++c) {
                     const int dz = r - c;
                     if (dz < 0 || dz > 2) continue;
-                    const double w = wxy * sw_l[6 + 2 - dz][kk];
+                    const R w = wxy * sw_l[6 + 2 - dz][kk];
 #pragma unroll
-                    for (int t = 0; t < NV; ++t) s[c][t] += w * v[t];
+                    for (int t = 0; t < NV; ++t) s[c][t] += (double)w * (double)v[t];
                 }
             }
         }
@@ -628,7 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_cells(Desc D, Cells<R> C)
     cell_coords(D.g, c, i, j, k);
     constexpr int NV = GatherNV<MODE>::v;
     double s[NV];
-    gather_cell<NV>(D, i, j, k, [&](int p, double *v) { gather_value<MODE>(D.pt, p, v); }, s);
+    gather_cell<R, NV>(D, i, j, k, [&](int p, double *v) { gather_value<MODE>(D.pt, p, v); }, s);
     gather_store<R, MODE>(D, C, c, s);
 }
 
@@ -1585,9 +1589,12 @@ template <typename R, int MODE> void launch_gather(const Desc &D, const Cells<R>
     } else if (v == 1) {
         dim3 grid((D.g.n[0] + 15) / 16, (D.g.n[1] + 3) / 4, (D.g.n[2] + 3) / 4);
         hipLaunchKernelGGL((k_gather_tile<R, MODE, 16, 4, 4, 1, 384>), grid, dim3(256), 0, s, D, C);
-    } else {
+    } else if (v == 2) {
         dim3 grid((D.g.n[0] + 7) / 8, (D.g.n[1] + 3) / 4, (D.g.n[2] + 3) / 4);
         hipLaunchKernelGGL((k_gather_tile<R, MODE, 8, 4, 4, 1, 640>), grid, dim3(128), 0, s, D, C);
+    } else {
+        dim3 grid((D.g.n[0] + 15) / 16, (D.g.n[1] + 3) / 4, (D.g.n[2] + 15) / 16);
+        hipLaunchKernelGGL((k_gather_tile<R, MODE, 16, 4, 4, 4, 512>), grid, dim3(256), 0, s, D, C);
     }
 }
 template <typename R> void launch_gather_am(const Desc &D, const Cells<R> &C, hipStream_t s)

@@ -95,32 +95,34 @@ def test_parity_periodic_settling_ragged(L):
     _one_step_parity(L, case, warm=3, nsteps=2)
 
 
-@pytest.mark.parametrize("eps", [0.03, 0.12])
-def test_gather_variants_bitwise_equal_and_match_oracle(L, eps):
-    """Every gather variant (LDS tiles of three shapes, tiles too crowded for
-    LDS that fall back to the per-cell gather, and the per-cell gather itself)
-    sums a cell's particles in the same order, so all give the same bits; two
+@pytest.mark.parametrize("eps,precision,tol", [(0.03, "fp64", TOL64), (0.12, "fp64", TOL64),
+                                               (0.12, "fp32dev", 1e-5)])
+def test_gather_variants_bitwise_equal_and_match_oracle(L, eps, precision, tol):
+    """Every gather variant (LDS tiles of four shapes, tiles too crowded for
+    LDS that fall back to the per-cell gather, and the per-cell gather itself
+    with the per-particle drag pass) sums a cell's particles in the same order
+    and precision, so all give the same bits in either storage form; two
     steps of them match the oracle. Edge 26 leaves ragged tiles on every axis."""
-    case = I.case_settling(7, 26, eps, 0.8, 2.5, precision="fp64")
-    _say(f"case {case.name} np {case.particles.n}")
+    case = I.case_settling(7, 26, eps, 0.8, 2.5, precision=precision)
+    _say(f"case {case.name} {precision} np {case.particles.n}")
     o = warm_oracle(case, 2, None)
     states = []
-    for v in range(4):
+    for v in range(5):
         with L.Domain(case.params) as dom:
             dom.lbdem_set_gather_variant(v)
             load_oracle_state(dom, o.state)
             dom.step(2)
             states.append(dom.lbdem_get_state())
     o.step(2)
-    errs, bad = compare_states(states[0], o.state, case.params, TOL64)
+    errs, bad = compare_states(states[0], o.state, case.params, tol)
     _say(f"  variant 0 vs oracle {errs}")
     assert not bad, errs
-    for v in range(1, 4):
+    for v in range(1, 5):
         for k, a in states[0].items():
             assert np.array_equal(np.asarray(states[v][k]), np.asarray(a)), (v, k)
     with L.Domain(case.params) as dom:
         with pytest.raises(L.LbdemError):
-            dom.lbdem_set_gather_variant(4)
+            dom.lbdem_set_gather_variant(5)
 
 
 def test_parity_crowded_small_spheres_list_capacity(L):

@@ -105,6 +105,35 @@ def test_fp64_free_running_drift(L):
     assert not bad, errs
 
 
+def test_small_walled_500_steps(L):
+    """The small walled workload (32x32x64, 64 spheres, FP64) over its full
+    500 steps: every step is compared at 1e-12 after advancing the GPU from
+    the oracle's own state; then the GPU runs the 500 steps on its own and its
+    drift from the oracle is reported (bounded by 1e-10)."""
+    case = I.case_small_walled(0)
+    o = O.Oracle(case.params, case.particles)
+    worst = {}
+    with L.Domain(case.params) as dom:
+        for s in range(500):
+            load_oracle_state(dom, o.state)
+            dom.step(1)
+            r = o.step(1)
+            assert r["status"] == 0
+            errs, bad = compare_states(dom.lbdem_get_state(), o.state, case.params, 1e-12)
+            for k, v in errs.items():
+                worst[k] = max(worst.get(k, 0.0), v)
+            assert not bad, (s, errs)
+    _say(f"  500 steps, worst per-step rel errors {worst}")
+    o2 = O.Oracle(case.params, case.particles)
+    with L.Domain(case.params) as dom:
+        dom.add(case.particles)
+        dom.step(500)
+        o2.step(500)
+        errs, bad = compare_states(dom.lbdem_get_state(), o2.state, case.params, 1e-10)
+    _say(f"  500-step free-running drift {errs}")
+    assert not bad, errs
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32dev", TOL32_STEP)])
 def test_full_size_dilute_one_step(L, precision, tol):
     """The benchmark workload at full size (128^3 cells, 391,139 spheres), one
