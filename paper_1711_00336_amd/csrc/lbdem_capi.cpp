@@ -274,8 +274,12 @@ void resolve_phys(lbdem_domain_t h)
     P.kn_per_m = (M_PI * M_PI + L * L) / (P.T_c * P.T_c);
     P.xi_per_m = -2.0 * L / P.T_c;
     P.c_am = p.c_am;
+    // a particle may move at most `skin` within one subcycle (else the step
+    // is flagged unstable); Verlet lists carry `vskin` beyond the interaction
+    // reach and are rebuilt once a particle has moved vskin/2 - skin since
+    // the build, so every pair within reach stays listed
     P.skin = 0.1;
-    P.vskin = 0.4;
+    P.vskin = 0.25;
     P.rbin = 1;
 }
 

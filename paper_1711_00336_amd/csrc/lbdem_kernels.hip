@@ -1211,7 +1211,9 @@ __global__ __launch_bounds__(kBlock) void k_integrate(Desc D, int last)
         }
     }
     if (bad) atomicOr(D.flags, bad);
-    if (P.pk) {
+    // the record feeds the next substep's pair loop; after the last substep
+    // of a subcycle the reorder rewrites every record
+    if (P.pk && !last) {
         const double uu[3] = {P.u[i], P.u[cap + i], P.u[2 * cap + i]};
         const double ww[3] = {P.w[i], P.w[cap + i], P.w[2 * cap + i]};
         store_rec(P.pk, i, x, uu, ww, d, P.rho[i]);

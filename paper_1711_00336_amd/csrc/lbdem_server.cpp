@@ -71,13 +71,13 @@ lbdem_status sfail(lbdem_status st, const std::string &m)
 
 // device bytes of one domain: two PDF buffers and 30 field components per
 // cell in the storage precision, bins, per-particle state, and the Verlet
-// lists (capacity twice the mean neighbour count within d_max + h_c + 0.4,
+// lists (capacity twice the mean neighbour count within d_max + h_c + 0.25,
 // plus 24 entries, as the domain sizes them)
 size_t footprint_of(const lbdem_params &p, int64_t np, double dmax)
 {
     const size_t nc = (size_t)p.n[0] * p.n[1] * p.n[2];
     const size_t rs = p.precision == LBDEM_FP64 ? 8 : 4;
-    const double reach = dmax + (p.use_lub ? std::max(p.h_c, 0.0) : 0.0) + 0.4;
+    const double reach = dmax + (p.use_lub ? std::max(p.h_c, 0.0) : 0.0) + 0.25;
     const double nbr = 2.0 * (double)np / (double)nc * (4.0 / 3.0) * M_PI * reach * reach * reach + 28.0;
     const size_t per_particle = 1100 + 4 * (size_t)std::max(32.0, nbr);
     return nc * (rs * (2 * 19 + 30) + 12) + (size_t)std::max<int64_t>(np, 64) * per_particle + (32u << 20);
