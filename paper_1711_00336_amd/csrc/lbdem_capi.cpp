@@ -374,9 +374,11 @@ void alloc_particles(lbdem_domain_t h, int64_t cap)
     for (int **v : ints) { h->dfree(*v); *v = nullptr; }
     h->dfree(P.sb);
     h->dfree(P.sw);
+    h->dfree(P.swf);
     h->dfree(h->list);
     P.sb = nullptr;
     P.sw = nullptr;
+    P.swf = nullptr;
     h->list = nullptr;
     P.cap = std::max<int64_t>(cap, 1);
     const size_t c = (size_t)P.cap;
@@ -403,9 +405,14 @@ void alloc_particles(lbdem_domain_t h, int64_t cap)
     hip_check(hipMemsetAsync(P.nnb, 0, sizeof(int) * c, h->stream), "hipMemsetAsync");
     hip_check(hipMemsetAsync(P.xbuild, 0, sizeof(double) * 3 * c, h->stream), "hipMemsetAsync");
     P.sb = (int *)h->dalloc(sizeof(int) * 3 * c);
-    P.sw = (double *)h->dalloc(sizeof(double) * 9 * c);
     hip_check(hipMemsetAsync(P.sb, 0, sizeof(int) * 3 * c, h->stream), "hipMemsetAsync");
-    hip_check(hipMemsetAsync(P.sw, 0, sizeof(double) * 9 * c, h->stream), "hipMemsetAsync");
+    if (h->prec == LBDEM_FP32_DEV) {
+        P.swf = (float *)h->dalloc(sizeof(float) * 9 * c);
+        hip_check(hipMemsetAsync(P.swf, 0, sizeof(float) * 9 * c, h->stream), "hipMemsetAsync");
+    } else {
+        P.sw = (double *)h->dalloc(sizeof(double) * 9 * c);
+        hip_check(hipMemsetAsync(P.sw, 0, sizeof(double) * 9 * c, h->stream), "hipMemsetAsync");
+    }
     h->list = (int *)h->dalloc(sizeof(int) * c);
     h->list_cap = P.cap;
     h->dfree(P.pk);

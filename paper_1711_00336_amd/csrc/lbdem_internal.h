@@ -81,7 +81,8 @@ struct Parts {
     double *x2, *u2, *w2, *a2, *d2, *rho2;  // permutation targets
     int *id2;
     int *sb;                    // [3][cap] kernel stencil base cell floor(x) per axis
-    double *sw;                 // [9][cap] per-axis kernel weights, (3*axis + o+1)*cap + i
+    double *sw;                 // [9][cap] per-axis kernel weights, (3*axis + o+1)*cap + i (FP64 form)
+    float *swf;                 // the same in FP32 (FP32-deviation form; exactly one of sw, swf is set)
     double *Fam, *Fd, *Fpr, *Fc;// current subcycle's fluid forces and F_const (slot order)
     double *Fdem, *Tdem;        // contact + lubrication force and torque of the substep
     double *ustart, *xstart;    // velocity / position at subcycle start

@@ -271,13 +271,24 @@ struct Stencil {
     double w[3][3];
 };
 
-__device__ __forceinline__ void load_stencil(const Parts &P, int64_t i, Stencil &st)
+// stored kernel weight u (= 3*axis + o+1) of slot p, in the storage precision
+template <typename R> __device__ __forceinline__ R stencil_weight(const Parts &P, int u, int64_t p);
+template <> __device__ __forceinline__ float stencil_weight<float>(const Parts &P, int u, int64_t p)
+{
+    return P.swf[u * P.cap + p];
+}
+template <> __device__ __forceinline__ double stencil_weight<double>(const Parts &P, int u, int64_t p)
+{
+    return P.sw[u * P.cap + p];
+}
+
+template <typename R> __device__ __forceinline__ void load_stencil(const Parts &P, int64_t i, Stencil &st)
 {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         st.b[a] = P.sb[a * P.cap + i];
 #pragma unroll
-        for (int o = 0; o < 3; ++o) st.w[a][o] = P.sw[(3 * a + o) * P.cap + i];
+        for (int o = 0; o < 3; ++o) st.w[a][o] = (double)stencil_weight<R>(P, 3 * a + o, i);
     }
 }
 
@@ -310,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
     if (i >= P.np) return;
     const int64_t nc = D.g.nc;
     Stencil st;
-    load_stencil(P, i, st);
+    load_stencil<R>(P, i, st);
     R Du[3] = {(R)0, (R)0, (R)0};
 #pragma unroll 1
     for (int oz = 0; oz < 3; ++oz) {
@@ -337,22 +348,22 @@ __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
 // neighbouring bins. Slots are sorted by cell, so each x-row of three bins is
 // one contiguous slot range.
 // ---------------------------------------------------------------------------
+template <typename R>
 __device__ __forceinline__ double stencil_w(const Parts &P, int64_t p, int axis, int ic, int n, int per)
 {
     const int b = P.sb[axis * P.cap + p];
-    const double *sw = P.sw + (int64_t)(3 * axis) * P.cap + p;
     int o = ic - b;
     if (per) {
         if (n < 3) {  // several stencil offsets land on the same cell
             double w = 0.0;
 #pragma unroll
             for (int t = -1; t <= 1; ++t)
-                if (wrap1(b + t, n) == ic) w += sw[(t + 1) * P.cap];
+                if (wrap1(b + t, n) == ic) w += (double)stencil_weight<R>(P, 3 * axis + t + 1, p);
             return w;
         }
         o = o > 1 ? o - n : (o < -1 ? o + n : o);
     }
-    return (o >= -1 && o <= 1) ? sw[(o + 1) * P.cap] : 0.0;
+    return (o >= -1 && o <= 1) ? (double)stencil_weight<R>(P, 3 * axis + o + 1, p) : 0.0;
 }
 
 // weights and values in the storage precision R, products accumulated in
@@ -362,9 +373,9 @@ __device__ __forceinline__ void gather_range(const Desc &D, int i, int j, int k,
                                              double *s)
 {
     for (int p = p0; p < p1; ++p) {
-        const R wx = (R)stencil_w(D.pt, p, 0, i, D.g.n[0], D.g.per[0]);
-        const R wy = (R)stencil_w(D.pt, p, 1, j, D.g.n[1], D.g.per[1]);
-        const R wz = (R)stencil_w(D.pt, p, 2, k, D.g.n[2], D.g.per[2]);
+        const R wx = (R)stencil_w<R>(D.pt, p, 0, i, D.g.n[0], D.g.per[0]);
+        const R wy = (R)stencil_w<R>(D.pt, p, 1, j, D.g.n[1], D.g.per[1]);
+        const R wz = (R)stencil_w<R>(D.pt, p, 2, k, D.g.n[2], D.g.per[2]);
         const R w = wx * wy * wz;
         if (w == (R)0) continue;
         double v[NV];
@@ -560,7 +571,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
             if (kk >= KMAX) break;
             const int p = src[t] + q;
 #pragma unroll
-            for (int u = 0; u < 9; ++u) sw_l[u][kk] = (R)P.sw[u * P.cap + p];
+            for (int u = 0; u < 9; ++u) sw_l[u][kk] = stencil_weight<R>(P, u, p);
             double v[NV];
             gather_value<MODE>(P, p, v);
 #pragma unroll
@@ -698,7 +709,7 @@ __global__ __launch_bounds__(kBlock) void k_part_drag(Desc D, Cells<R> C, int re
     if (i >= P.np) return;
     const int64_t nc = D.g.nc;
     Stencil st;
-    load_stencil(P, i, st);
+    load_stencil<R>(P, i, st);
     R uf[3] = {(R)0, (R)0, (R)0}, gp[3] = {(R)0, (R)0, (R)0}, ep = (R)0;
 #pragma unroll 1
     for (int oz = 0; oz < 3; ++oz) {
@@ -815,7 +826,7 @@ __global__ __launch_bounds__(256) void k_part_tile(Desc D, Cells<R> C, int recor
         }
         const int64_t i = rsrc[lo] + (k - rp[lo]);
         Stencil st;
-        load_stencil(P, i, st);
+        load_stencil<R>(P, i, st);
         // the stencil base is the particle's bin, inside this tile; the clamp
         // only keeps LDS indices in range for a particle already flagged as
         // having left the domain
@@ -1359,8 +1370,13 @@ __global__ __launch_bounds__(kBlock) void k_permute(Desc D)
         double wt[3];
         axis_weights(x[a], D.g.n[a], D.g.per[a], b, wt);
         P.sb[a * cap + s] = b;
+        if (P.swf) {
 #pragma unroll
-        for (int o = 0; o < 3; ++o) P.sw[(3 * a + o) * cap + s] = wt[o];
+            for (int o = 0; o < 3; ++o) P.swf[(3 * a + o) * cap + s] = (float)wt[o];
+        } else {
+#pragma unroll
+            for (int o = 0; o < 3; ++o) P.sw[(3 * a + o) * cap + s] = wt[o];
+        }
     }
     const double d = P.d[src], rho = P.rho[src];
     P.d2[s] = d;
