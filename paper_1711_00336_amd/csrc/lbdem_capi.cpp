@@ -64,7 +64,7 @@ struct lbdem_domain {
     void *drho = nullptr, *j = nullptr, *uprev = nullptr, *un = nullptr, *dudt = nullptr, *gradp = nullptr;
     void *epsp = nullptr, *fam = nullptr, *uf = nullptr, *facc = nullptr;
     // bins
-    int *cnt = nullptr, *start = nullptr, *list = nullptr, *bsum = nullptr;
+    int *cnt = nullptr, *start = nullptr, *list = nullptr, *bsum = nullptr, *loc = nullptr;
     int64_t list_cap = 0;
     int64_t nlist_rows = 0;     // particle rows the Verlet-list buffer holds
     // particles
@@ -137,7 +137,7 @@ struct lbdem_domain {
         D.g = geo;
         D.p = phys;
         D.t = tune;
-        D.b = Bins{cnt, start, list, bsum};
+        D.b = Bins{cnt, start, list, bsum, loc};
         D.pt = pt;
         D.flags = flags;
         D.stepc = stepc;
@@ -748,6 +748,7 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
         h->cnt = (int *)h->dalloc(sizeof(int) * nc);
         h->start = (int *)h->dalloc(sizeof(int) * (nc + 1));
         h->bsum = (int *)h->dalloc(sizeof(int) * ((nc + kScanPerBlock - 1) / kScanPerBlock + 1));
+        h->loc = (int *)h->dalloc(sizeof(int) * nc);
         h->flags = (int *)h->dalloc(sizeof(int) * 4);
         h->stepc = (long long *)h->dalloc(sizeof(long long) * 2);
         h->pt.need = (int *)h->dalloc(sizeof(int) * 4);

@@ -53,7 +53,8 @@ struct Bins {
     int *cnt;                   // [nc] counts (zero between builds)
     int *start;                 // [nc+1] exclusive prefix of cnt = slot ranges after the permutation
     int *list;                  // [np] slot indices, ordered by (cell, id) before the permutation
-    int *bsum;                  // scan block sums
+    int *bsum;                  // scan block sums (exclusive prefix after the top-level scan)
+    int *loc;                   // [nc] prefix of cnt within its scan block
 };
 
 // Packed copy of what a DEM pair evaluation reads of a neighbour, one 64-byte

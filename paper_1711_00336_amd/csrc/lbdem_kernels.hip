@@ -1247,7 +1247,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(Desc D)
 // exclusive scan of cnt into start (block level); resets cnt
 __global__ __launch_bounds__(kBlock) void k_scan_block(Desc D)
 {
-    __shared__ int sh[kBlock];
+    __shared__ int wsum[kBlock / 64];
     const int64_t nc = D.g.nc;
     const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + (int64_t)threadIdx.x * kScanItems;
     int v[kScanItems];
@@ -1258,25 +1258,33 @@ __global__ __launch_bounds__(kBlock) void k_scan_block(Desc D)
         v[t] = c < nc ? D.b.cnt[c] : 0;
         tot += v[t];
     }
-    sh[threadIdx.x] = tot;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const int add = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
-        __syncthreads();
-        sh[threadIdx.x] += add;
-        __syncthreads();
+    // wavefront-shuffle scan, then the wavefront totals (one barrier)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
     }
-    int run = sh[threadIdx.x] - tot;
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int run = incl - tot, btot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const int ws = wsum[w];
+        if (w < wv) run += ws;
+        btot += ws;
+    }
 #pragma unroll
     for (int t = 0; t < kScanItems; ++t) {
         const int64_t c = base + t;
         if (c < nc) {
-            D.b.start[c] = run;
+            D.b.loc[c] = run;
             D.b.cnt[c] = 0;
         }
         run += v[t];
     }
-    if (threadIdx.x == kBlock - 1) D.b.bsum[blockIdx.x] = sh[kBlock - 1];
+    if (threadIdx.x == kBlock - 1) D.b.bsum[blockIdx.x] = btot;
 }
 
 // exclusive scan of the block sums, one block of 1024 threads
@@ -1306,11 +1314,10 @@ __global__ __launch_bounds__(1024) void k_scan_top(int *bsum, int nb, int *total
     if (threadIdx.x == 1023) *total = sh[1023];
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_add(Desc D)
+// slot range start of bin c from the block-local prefix and the block offset
+__device__ __forceinline__ int bin_start(const Bins &B, int64_t c)
 {
-    const int64_t nc = D.g.nc;
-    const int64_t c = gidx();
-    if (c < nc) D.b.start[c] += D.b.bsum[c / kScanPerBlock];
+    return B.loc[c] + B.bsum[c / kScanPerBlock];
 }
 
 __global__ __launch_bounds__(kBlock) void k_place(Desc D)
@@ -1320,19 +1327,20 @@ __global__ __launch_bounds__(kBlock) void k_place(Desc D)
     if (i >= P.np) return;
     const int64_t cap = P.cap;
     const int64_t c = particle_cell(D.g, P.x[i], P.x[cap + i], P.x[2 * cap + i]);
-    const int pos = D.b.start[c] + atomicAdd(&D.b.cnt[c], 1);
+    const int pos = bin_start(D.b, c) + atomicAdd(&D.b.cnt[c], 1);
     D.b.list[pos] = (int)i;
 }
 
 // order each bin by insertion index (so that every sum over a bin runs in a
-// history-independent order) and reset the counts
+// history-independent order), write the final bin offsets, reset the counts
 __global__ __launch_bounds__(kBlock) void k_cellsort(Desc D)
 {
     const int64_t nc = D.g.nc;
     const int64_t c = gidx();
     if (c >= nc) return;
     D.b.cnt[c] = 0;
-    const int p0 = D.b.start[c], p1 = D.b.start[c + 1];
+    const int p0 = bin_start(D.b, c), p1 = c + 1 < nc ? bin_start(D.b, c + 1) : D.b.start[nc];
+    D.b.start[c] = p0;
     const int *id = D.pt.id;
     int *L = D.b.list;
     for (int a = p0 + 1; a < p1; ++a) {
@@ -1699,7 +1707,6 @@ void launch_bin_build(const Desc &D, hipStream_t s)
     const unsigned nb = nblocks(D.g.nc, kScanPerBlock);
     hipLaunchKernelGGL(k_scan_block, dim3(nb), dim3(kBlock), 0, s, D);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, D.b.bsum, (int)nb, D.b.start + D.g.nc);
-    hipLaunchKernelGGL(k_scan_add, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D);
     if (D.pt.np > 0) hipLaunchKernelGGL(k_place, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
 }
 void launch_sort_permute(const Desc &D, hipStream_t s)
