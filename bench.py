@@ -4,6 +4,7 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dilute|dilute64|small|dense]
     python bench.py --mode batch [--domains 256] [--steps K]
     python bench.py --mode serve [--requests R] [--rates 10,100]
+    python bench.py --mode k10      (stream-collide alone on 256x256x512)
 
 A step is one full coupled time step (Alg. 1 of the paper): moments, Du_f/Dt
 and grad P, n_int interaction subcycles (added mass, drag, pressure and
@@ -136,11 +137,12 @@ PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1711_00336_amd", "csrc", "lbdem_kernels.hip")
 
 
-def measured_traffic(kernel_class, workload_name):
+def measured_traffic(kernel_class, workload_name, gather_variant=None):
     """HBM bytes per launch from the committed rocprofv3 counter summary of
     this kernel and workload (FETCH_SIZE + WRITE_SIZE, each scaled by the
     same counter on a plain device copy of known size), or None when there is
-    none or the kernel source has changed since the counters were taken."""
+    none, when the kernel source has changed since the counters were taken,
+    or when the summary was taken with another gather variant."""
     import hashlib
     path = os.path.join(PROFILES, f"traffic_{kernel_class}_{workload_name}.md")
     if not os.path.exists(path):
@@ -152,6 +154,8 @@ def measured_traffic(kernel_class, workload_name):
             vals[k.strip()] = v.strip().strip("`")
     src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     if vals.get("kernel_source_sha256") != src:
+        return None
+    if gather_variant is not None and "gather_variant" in vals and int(vals["gather_variant"]) != gather_variant:
         return None
     try:
         return int(float(vals["hbm_bytes_per_launch"]))
@@ -183,7 +187,8 @@ def k10_roofline(lbdem, stream, steps=10, warmup=3):
     ach = byts / (avg * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": "stream_collide", "workload": "fluid-256x256x512-fp32dev",
             "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("stream_collide", "fluid-256x256x512"),
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("stream_collide", "fluid-256x256x512"),
             "bytes_per_launch": byts, "avg_launch_ms": round(avg, 5)}
 
 
@@ -405,7 +410,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--mode", choices=("step", "batch", "serve"), default="step")
+    ap.add_argument("--mode", choices=("step", "batch", "serve", "k10"), default="step")
     ap.add_argument("--domains", type=int, default=256)
     ap.add_argument("--requests", type=int, default=16)
     ap.add_argument("--rates", default="10,1000")
@@ -419,9 +424,9 @@ def main():
     args = ap.parse_args()
     dense = args.mode == "step" and args.workload == "dense"
     if args.steps is None:
-        args.steps = 10 if dense else {"step": 200, "batch": 20, "serve": 0}[args.mode]
+        args.steps = 10 if dense else {"step": 200, "batch": 20, "serve": 0, "k10": 0}[args.mode]
     if args.warmup is None:
-        args.warmup = 3 if dense else {"step": 20, "batch": 3, "serve": 0}[args.mode]
+        args.warmup = 3 if dense else {"step": 20, "batch": 3, "serve": 0, "k10": 0}[args.mode]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
               "(the spatial decomposition across GPUs is a design, not part of this build)", file=sys.stderr)
@@ -430,6 +435,13 @@ def main():
         return bench_batch(args)
     if args.mode == "serve":
         return bench_serve(args)
+    if args.mode == "k10":
+        import torch
+        from paper_1711_00336_amd import lbdem
+        torch.cuda.init()
+        print(json.dumps({"mode": "k10", "roofline_stream_collide": k10_roofline(lbdem, torch.cuda.current_stream())}),
+              flush=True)
+        return
 
     import torch
     from paper_1711_00336_amd import lbdem
@@ -482,7 +494,7 @@ def main():
     achieved = kb[dom_cls] / (kt["avg_launch_ms"] * 1e-3) / 1e9 if kt["avg_launch_ms"] > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": dom_cls, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom_cls, args.workload), "bytes_per_launch": kb[dom_cls],
+                "traffic": measured_traffic(dom_cls, args.workload, variant), "bytes_per_launch": kb[dom_cls],
                 "avg_launch_ms": round(kt["avg_launch_ms"], 5), "share_of_step": round(kt["ms_per_step"] / sum(
                     v["ms_per_step"] for v in times.values()), 4)}
     if dom_cls == "dem_force":
