@@ -148,3 +148,38 @@ def test_full_size_dilute_one_step(L, precision, tol):
         errs, bad = compare_states(dom.lbdem_get_state(), o.state, case.params, tol)
     _say(f"  full-size rel errors {errs}")
     assert not bad, errs
+
+
+def _settle(L, case, steps, avg_last):
+    with L.Domain(case.params) as dom:
+        dom.add(case.particles)
+        dom.step(steps - avg_last)
+        ups = []
+        for _ in range(avg_last):
+            dom.step(1)
+            ups.append(dom.lbdem_diagnostics()["u_ps"])
+        d = dom.lbdem_diagnostics()
+    return float(np.mean(ups)), d
+
+
+def test_dilute_bench_workload_settling_2000_steps(L):
+    """The dilute benchmark workload at full size and length (128^3 cells,
+    391,139 spheres, 2000 steps, <u_pS> averaged over the last 500): the FP32
+    form against the FP64 path (itself checked against the oracle step by
+    step in the parity tests) within max(1 %, twice the FP64 chaos floor),
+    the floor being the change of the FP64 result when every position is
+    moved by 1e-12; mean porosity within 1e-6."""
+    c64 = I.case_dilute_periodic(0, n=128, eps_p=0.05, d=0.8, precision="fp64")
+    c32 = I.case_dilute_periodic(0, n=128, eps_p=0.05, d=0.8, precision="fp32dev")
+    pert = I.case_dilute_periodic(0, n=128, eps_p=0.05, d=0.8, precision="fp64")
+    pert.particles.x[:] = pert.particles.x + 1e-12
+    u64, d64 = _settle(L, c64, 2000, 500)
+    _say(f"  fp64 <u_pS> {u64:.6e}")
+    u64p, _ = _settle(L, pert, 2000, 500)
+    u32, d32 = _settle(L, c32, 2000, 500)
+    floor = abs(u64p - u64) / abs(u64)
+    rel = abs(u32 - u64) / abs(u64)
+    e_eps = abs(d32["mean_eps_f"] - d64["mean_eps_f"]) / d64["mean_eps_f"]
+    _say(f"  fp32 <u_pS> {u32:.6e} rel {rel:.2e}; chaos floor {floor:.2e}; <eps_f> rel {e_eps:.2e}")
+    assert rel <= max(0.01, 2.0 * floor)
+    assert e_eps <= TOL_EPS
