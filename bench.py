@@ -428,8 +428,8 @@ def main():
     if args.warmup is None:
         args.warmup = 3 if dense else {"step": 20, "batch": 3, "serve": 0, "k10": 0}[args.mode]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(the spatial decomposition across GPUs is a design, not part of this build)", file=sys.stderr)
+        print("bench.py: this library runs on one GPU only; --gpus must be 1 "
+              "(the spatial decomposition across GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.mode == "batch":
         return bench_batch(args)

@@ -762,7 +762,7 @@ void orc_diagnostics(const orc_params *p, const orc_state *s, orc_diag *out)
  *       Sec. 3.2.3 stability measures).
  *   S2  n_int interaction subcycles, each:
  *       (a) f_ext := eps_f f_b                   (external body force)
- *       (b) grad P  (lift and curl are not part of this build)
+ *       (b) grad P  (lift and curl are not implemented)
  *       (c) F_am per particle, distributed to f_ext
  *       (d) re-evaluate u_f with the updated f_ext
  *       (e) F_pr, F_d per particle, F_d distributed; F_g (+ buoyancy)
