@@ -150,3 +150,24 @@ def test_server_cancel(L):
         r1, r2 = srv.wait(t1), srv.wait(t2)
         assert r1["status"] == L.E_STATE and r2["status"] == L.E_STATE
         assert r1["steps_done"] < 400
+
+
+def test_server_unstable_request_fails_alone(L):
+    """A request in the unstable corner of the explicit coupling (tau = 0.7,
+    light crowded spheres: the FP64 oracle diverges at step 5 on it) ends
+    with LBDEM_E_UNSTABLE and frees its memory and slot; a request running
+    beside it is unaffected (its result equals the same request alone)."""
+    bad = I.case_settling(23, 18, 0.3, 0.8, 2.0, precision="fp32dev", tau=0.7)
+    good = I.case_settling(11, 20, 0.08, 0.8, 2.5, precision="fp32dev")
+    with L.Server(8 << 30, max_slots=4, chunk_steps=10) as srv:
+        tg = srv.lbdem_server_submit(good.params, good.particles, 60, 20)
+        alone = srv.wait(tg)
+    with L.Server(8 << 30, max_slots=4, chunk_steps=10) as srv:
+        tb = srv.lbdem_server_submit(bad.params, bad.particles, 300, 0)
+        tg = srv.lbdem_server_submit(good.params, good.particles, 60, 20)
+        rb, rg = srv.wait(tb), srv.wait(tg)
+        st = srv.lbdem_server_stats()
+    _say(f"  unstable request: status {rb['status']} after {rb['steps_done']} steps")
+    assert rb["status"] == L.E_UNSTABLE and rb["steps_done"] < 300
+    assert rg["status"] == 0 and rg["u_ps"] == alone["u_ps"]
+    assert st["active"] == 0 and st["queued"] == 0 and st["bytes"] == 0
