@@ -632,9 +632,15 @@ void read_field_impl(lbdem_domain_t h, int field, double *dev_out)
         break;
     }
     case LBDEM_FIELD_J: src = (const R *)h->j; ncomp = 3; break;
-    case LBDEM_FIELD_EPS_F: src = (const R *)h->epsp; break;
+    case LBDEM_FIELD_EPS_F:
+        launch_fluid_fraction<R>((const R *)h->epsp, dev_out, nc, h->stream);
+        hip_check(hipGetLastError(), "read_field");
+        return;
     case LBDEM_FIELD_F_ACC: src = (const R *)h->facc; ncomp = 3; break;
-    case LBDEM_FIELD_DUDT: src = (const R *)h->dudt; ncomp = 3; break;
+    case LBDEM_FIELD_DUDT:
+        launch_vec4_to_double<R>((const R *)h->dudt, dev_out, nc, h->stream);
+        hip_check(hipGetLastError(), "read_field");
+        return;
     case LBDEM_FIELD_GRADP: src = (const R *)h->gradp; ncomp = 3; break;
     case LBDEM_FIELD_UPREV: src = (const R *)h->uprev; ncomp = 3; break;
     case LBDEM_FIELD_PDF: src = (const R *)h->df[h->cur]; ncomp = 19; break;
@@ -739,7 +745,7 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
         h->j = h->dalloc(rs * 3 * nc);
         h->uprev = h->dalloc(rs * 3 * nc);
         h->un = h->dalloc(rs * 3 * nc);
-        h->dudt = h->dalloc(rs * 3 * nc);
+        h->dudt = h->dalloc(rs * 4 * nc);
         h->gradp = h->dalloc(rs * 3 * nc);
         h->epsp = h->dalloc(rs * nc);
         h->fam = h->dalloc(rs * 3 * nc);
@@ -757,8 +763,9 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
         h->diag_out = (double *)h->dalloc(sizeof(double) * 16);
         for (void *q : {h->df[0], h->df[1]}) hip_check(hipMemsetAsync(q, 0, rs * 19 * nc, h->stream), "memset");
         for (void *q : {h->drho, h->epsp}) hip_check(hipMemsetAsync(q, 0, rs * nc, h->stream), "memset");
-        for (void *q : {h->j, h->uprev, h->un, h->dudt, h->gradp, h->fam, h->uf, h->facc})
+        for (void *q : {h->j, h->uprev, h->un, h->gradp, h->fam, h->uf, h->facc})
             hip_check(hipMemsetAsync(q, 0, rs * 3 * nc, h->stream), "memset");
+        hip_check(hipMemsetAsync(h->dudt, 0, rs * 4 * nc, h->stream), "memset");
         hip_check(hipMemsetAsync(h->cnt, 0, sizeof(int) * nc, h->stream), "memset");
         hip_check(hipMemsetAsync(h->start, 0, sizeof(int) * (nc + 1), h->stream), "memset");
         hip_check(hipMemsetAsync(h->flags, 0, sizeof(int) * 4, h->stream), "memset");

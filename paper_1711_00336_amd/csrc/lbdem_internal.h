@@ -40,7 +40,7 @@ struct Cells {
     R *j;                       // [3] sum_q c_q f_q at step start
     R *uprev;                   // [3] u_f of the previous step
     R *un;                      // [3] u_f of the current post-stream state
-    R *dudt;                    // [3] Du_f/Dt
+    R *dudt;                    // [nc][4] Du_f/Dt as (x, y, z, 0) per cell
     R *gradp;                   // [3] grad P
     R *epsp;                    // solid fraction 1 - eps_f of the current positions
     R *fam;                     // [3] -sum_p D F_am of the current subcycle
@@ -139,6 +139,8 @@ constexpr int kGatherVariants = 5;
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s);
 template <typename R> void launch_to_double(const R *src, double *dst, int64_t n, hipStream_t s);
+template <typename R> void launch_vec4_to_double(const R *src, double *dst, int64_t nc, hipStream_t s);
+template <typename R> void launch_fluid_fraction(const R *src, double *dst, int64_t nc, hipStream_t s);
 template <typename R> void launch_from_double(const double *src, R *dst, int64_t n, hipStream_t s);
 template <typename R>
 void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials, int nblk, double *out,

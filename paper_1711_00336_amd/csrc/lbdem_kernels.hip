@@ -157,6 +157,32 @@ __device__ __forceinline__ int64_t particle_cell(const Geo &g, double x, double 
 
 __device__ __forceinline__ double sphere_volume(double d) { return M_PI * d * d * d / 6.0; }
 
+// 4-vector cell fields ([nc][4], components x, y, z, 0): one 16- or 32-byte
+// access per cell instead of three scattered ones
+__device__ __forceinline__ void store_vec4(float *p, float a, float b, float c)
+{
+    *reinterpret_cast<float4 *>(p) = make_float4(a, b, c, 0.0f);
+}
+__device__ __forceinline__ void store_vec4(double *p, double a, double b, double c)
+{
+    reinterpret_cast<double2 *>(p)[0] = make_double2(a, b);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(c, 0.0);
+}
+__device__ __forceinline__ void load_vec4(const float *p, float v[3])
+{
+    const float4 t = *reinterpret_cast<const float4 *>(p);
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+}
+__device__ __forceinline__ void load_vec4(const double *p, double v[3])
+{
+    const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+}
+
 // ---------------------------------------------------------------------------
 // a1: moments of the post-stream PDFs (Eq. MacVel): rho - 1 = sum df,
 // j = sum c df (exact with deviations since sum_q w_q c_q = 0).
@@ -248,17 +274,19 @@ __global__ __launch_bounds__(kBlock) void k_cellfields(Desc D, Cells<R> C)
     un[1] = (double)C.un[nc + c];
     un[2] = (double)C.un[2 * nc + c];
     const bool have_prev = *D.stepc > 0;
+    R du[3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
         double conv = 0.0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) conv += un[a] * (3.0 * G[a][b]);
         const double dtu = have_prev ? (un[b] - (double)C.uprev[b * nc + c]) : 0.0;
-        C.dudt[b * nc + c] = (R)(dtu + conv);
+        du[b] = (R)(dtu + conv);
         C.gradp[b * nc + c] = (R)gp[b];
         C.uprev[b * nc + c] = (R)un[b];
         C.facc[b * nc + c] = (R)0;
     }
+    store_vec4(C.dudt + 4 * c, du[0], du[1], du[2]);
 }
 
 // ---------------------------------------------------------------------------
@@ -334,8 +362,10 @@ __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
                 const int cx = stencil_coord(st.b[0], ox - 1, D.g.n[0], D.g.per[0]);
                 const int64_t cell = cidx(D.g, cx, cy, cz);
                 const R w = (R)(st.w[0][ox] * st.w[1][oy] * sel3(st.w[2], oz));
+                R v[3];
+                load_vec4(C.dudt + 4 * cell, v);
 #pragma unroll
-                for (int b = 0; b < 3; ++b) Du[b] += w * C.dudt[b * nc + cell];
+                for (int b = 0; b < 3; ++b) Du[b] += w * v[b];
             }
         }
     }
@@ -796,8 +826,7 @@ __global__ __launch_bounds__(256) void k_part_tile(Desc D, Cells<R> C, int recor
             const int gz = stencil_coord(z0, hz - 1, n2, D.g.per[2]);
             const int64_t cell = cidx(D.g, gx, gy, gz);
             if (PASS == PASS_AM) {
-#pragma unroll
-                for (int b = 0; b < 3; ++b) v[b] = C.dudt[b * nc + cell];
+                load_vec4(C.dudt + 4 * cell, v);
             } else {
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
@@ -1561,6 +1590,23 @@ __global__ void k_convert(const A *src, B *dst, int64_t n)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = (B)src[i];
 }
 
+// stored solid fraction -> fluid volume fraction 1 - eps_p, FP64
+template <typename A> __global__ void k_fluid_fraction(const A *src, double *dst, int64_t nc)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += stride)
+        dst[c] = 1.0 - (double)src[c];
+}
+
+// [nc][4] -> [3][nc] doubles
+template <typename A> __global__ void k_vec4_to_soa(const A *src, double *dst, int64_t nc)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += stride)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) dst[b * nc + c] = (double)src[4 * c + b];
+}
+
 __global__ void k_set_step(long long *s, long long v) { *s = v; }
 __global__ void k_set_int(int *p, int v) { *p = v; }
 
@@ -1593,9 +1639,11 @@ template <typename R> void launch_part_am(const Desc &D, const Cells<R> &C, hipS
 {
     if (D.pt.np > 0) hipLaunchKernelGGL(k_part_am<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
 }
-// tile shapes (chosen per domain by the autotuner, else by particle density):
-// 0: 16x4x4 cells, up to 384 staged particles; 1: 8x4x4, 512; 2: 8x8x4, 512.
-// All give bit-identical results: every cell sums its bins in the same order.
+// gather variants (chosen per domain by the autotuner, else by particle
+// density): 0 tiles of 16x4x8 cells (two per thread, up to 256 staged
+// particles); 1 16x4x4 (384); 2 8x4x4 (640); 3 one thread per cell from
+// global memory; 4 16x4x16 (four per thread, 512). All give bit-identical
+// results: every cell sums its bins in the same order and precision.
 // Periodic axes thinner than 3 cells use the per-cell gather.
 template <typename R, int MODE> void launch_gather(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
@@ -1658,6 +1706,16 @@ template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &
 template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s)
 {
     if (n > 0) hipLaunchKernelGGL(k_zero<R>, dim3(grid_stride_blocks(n)), dim3(kBlock), 0, s, p, n);
+}
+template <typename R> void launch_fluid_fraction(const R *src, double *dst, int64_t nc, hipStream_t s)
+{
+    if (nc > 0)
+        hipLaunchKernelGGL((k_fluid_fraction<R>), dim3(grid_stride_blocks(nc)), dim3(kBlock), 0, s, src, dst, nc);
+}
+template <typename R> void launch_vec4_to_double(const R *src, double *dst, int64_t nc, hipStream_t s)
+{
+    if (nc > 0)
+        hipLaunchKernelGGL((k_vec4_to_soa<R>), dim3(grid_stride_blocks(nc)), dim3(kBlock), 0, s, src, dst, nc);
 }
 template <typename R> void launch_to_double(const R *src, double *dst, int64_t n, hipStream_t s)
 {
@@ -1736,6 +1794,8 @@ void launch_set_step(long long *stepc, long long v, hipStream_t s)
     template void launch_stream_collide<R>(const Desc &, const Cells<R> &, hipStream_t);                   \
     template void launch_zero<R>(R *, int64_t, hipStream_t);                                                \
     template void launch_to_double<R>(const R *, double *, int64_t, hipStream_t);                          \
+    template void launch_vec4_to_double<R>(const R *, double *, int64_t, hipStream_t);                     \
+    template void launch_fluid_fraction<R>(const R *, double *, int64_t, hipStream_t);                     \
     template void launch_from_double<R>(const double *, R *, int64_t, hipStream_t);                        \
     template void launch_diag<R>(const Desc &, const Cells<R> &, const R *, double *, int, double *, hipStream_t);
 

@@ -132,6 +132,35 @@ def test_parity_crowded_small_spheres_list_capacity(L):
     _one_step_parity(L, case, warm=1, nsteps=2)
 
 
+@pytest.mark.parametrize("walled", [False, True])
+def test_fields_and_particle_forces_match_oracle(L, walled):
+    """The fields and forces a user reads after a step, against the oracle's
+    own values of the same step: Du_f/Dt, grad P, the subcycle-mean force
+    density f_acc, the fluid volume fraction eps_f of the new positions, the
+    momentum density j at the step's start, and the last subcycle's F_am,
+    F_d, F_pr and F_const of every particle (insertion order)."""
+    if walled:
+        case = I.case_small_walled(4)
+    else:
+        case = I.case_settling(13, 22, 0.12, 0.8, 2.5, precision="fp64")
+    o = warm_oracle(case, 2)
+    with L.Domain(case.params) as dom:
+        load_oracle_state(dom, o.state)
+        dom.step(1)
+        aux = o.step(1, aux=True)
+        assert aux["status"] == 0
+        got = {
+            "dudt": dom.lbdem_read_field(L.FIELD_DUDT), "gradp": dom.lbdem_read_field(L.FIELD_GRADP),
+            "f_acc": dom.lbdem_read_field(L.FIELD_F_ACC), "eps_f": dom.lbdem_read_field(L.FIELD_EPS_F),
+            "j": dom.lbdem_read_field(L.FIELD_J),
+        }
+        got.update(dom.lbdem_read_particle_forces())
+    errs = {k: rel_err(got[k], aux[k]) for k in got}
+    _say(f"  fields and forces rel errors {errs}")
+    bad = {k: v for k, v in errs.items() if not v <= TOL64}
+    assert not bad, bad
+
+
 def test_parity_degenerate_thin_periodic_axis(L):
     """A periodic axis of 2 cells: kernel stencils and neighbour bins wrap onto
     themselves."""
