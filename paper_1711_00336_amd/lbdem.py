@@ -78,6 +78,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"HIP library not built: {LIB_PATH} (run python -m paper_1711_00336_amd.build)")
+        # PyTorch wheels bring their own HIP runtime and a process can use only
+        # one: loading torch first (when installed) binds this library to the
+        # runtime torch uses, so device pointers, streams and the caching
+        # allocator can be shared with it whatever the import order.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         H = C.c_void_p
         st = C.c_int
@@ -408,6 +416,37 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_allocator_refs = []
+
+
+def use_torch_allocator(enable=True):
+    """Route the device allocations of domains created from now on through
+    PyTorch's caching allocator (lbdem_set_allocator), or back to
+    hipMalloc/hipFree with enable=False. Domains free their memory after
+    synchronising their stream, so torch reuses a block only once the
+    library is done with it."""
+    if not enable:
+        _check(None, lib().lbdem_set_allocator(None, None, None))
+        _allocator_refs.clear()
+        return
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except RuntimeError:
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = _ALLOC_FN(_alloc), _FREE_FN(_free)
+    _check(None, lib().lbdem_set_allocator(C.cast(a, C.c_void_p), C.cast(f, C.c_void_p), None))
+    _allocator_refs[:] = [a, f]
 
 
 def exported_symbols():
