@@ -22,6 +22,8 @@
  *     conditions of the kernel, partition of unity, closed-form porosity).
  *   - Drag, lubrication, contact forces: pinned (closed forms, limits,
  *     restitution, rolling, antisymmetry).
+ *   - Lattice curl and lift: pinned (closed-form curl of sinusoidal and
+ *     wall-bounded linear fields; Saffman's lift in a linear shear).
  *   - Du_f/Dt time discretisation, a_p lag, subcycle averaging of the fluid
  *     force, near-wall kernel renormalisation: parity unpinned against the
  *     paper (the paper does not fix them); checked by invariants only.
@@ -74,6 +76,7 @@ typedef struct {
     int32_t lub_stab, use_lub, use_am;
     int32_t n_int, n_dem;
     double c_am;
+    int32_t use_lift;  /* shear-induced lift (Table 1) on/off */
 } orc_params;
 
 typedef struct {
@@ -99,6 +102,8 @@ typedef struct {
     double impulse_fb[3];  /* (1/n_int) sum_k sum_x eps_f f_b */
     double min_eps_f;
     int32_t status;        /* 0 ok, 3 unstable */
+    double *F_l;           /* [np][3] lift, last subcycle (zero with lift off) */
+    double *curl;          /* [3][Nc] curl of u_f at the last subcycle's start (lift on) */
 } orc_aux;
 
 static int64_t NC(const orc_params *p) { return (int64_t)p->n[0] * p->n[1] * p->n[2]; }
@@ -356,6 +361,35 @@ static int64_t ghost_cell(const orc_params *p, int i, int j, int k, int q, doubl
     return CIDX(p, t[0], t[1], t[2]);
 }
 
+static void cross(const double a[3], const double b[3], double c[3]);
+static double dot(const double a[3], const double b[3]);
+
+/* Lattice curl (Sec. 3.2.3, rotation of a vector field):
+ *   curl psi(x) ~ (1/c_s^2) sum_q w_q c_q x psi(x + c_q)
+ * applied to a velocity field with the ghost rule above. u, out: [3][Nc]. */
+void orc_curl_field(const orc_params *p, const double *u, double *out)
+{
+    const int64_t nc = NC(p);
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < p->n[2]; ++k)
+        for (int jj = 0; jj < p->n[1]; ++jj)
+            for (int i = 0; i < p->n[0]; ++i) {
+                const int64_t c = CIDX(p, i, jj, k);
+                double s[3] = {0.0, 0.0, 0.0};
+                for (int q = 0; q < Q; ++q) {
+                    double sg, cq[3], v[3], cv[3];
+                    int64_t nb = ghost_cell(p, i, jj, k, q, &sg);
+                    for (int a = 0; a < 3; ++a) {
+                        cq[a] = CV[q][a];
+                        v[a] = sg * u[a * nc + nb];
+                    }
+                    cross(cq, v, cv);
+                    for (int a = 0; a < 3; ++a) s[a] += WQ(q) * cv[a];
+                }
+                for (int a = 0; a < 3; ++a) out[a * nc + c] = 3.0 * s[a];
+            }
+}
+
 /* ---------------------------------------------------------------------------
  * Drag (Sec. 3.1.2, Table 1; Tenneti et al. correlation as printed):
  *   F_d = 3 pi d mu0 (1 - eps_p) C_d(Re, eps_p) (u_f|p - u_p)
@@ -382,6 +416,23 @@ void orc_drag(double d, double mu, double rho_f, double ep, const double w[3], d
     double Re = (1.0 - ep) * rho_f * d * wn / mu;
     double fac = 3.0 * M_PI * d * mu * orc_drag_factor(Re, ep);
     for (int a = 0; a < 3; ++a) F[a] = fac * w[a];
+}
+
+/* Shear-induced lift (Table 1, after Saffman):
+ *   F_l = 1.61 d^2 sqrt(mu0 rho_f / |omega|) (w x omega)
+ * with w = u_f|p - u_p and omega = (curl u_f)|p. Reading: F_l = 0 where
+ * omega = 0, the limit of the formula (its magnitude scales with sqrt|omega|). */
+void orc_lift(double d, double mu, double rho_f, const double w[3], const double om[3], double F[3])
+{
+    const double on = sqrt(dot(om, om));
+    if (on == 0.0) {
+        F[0] = F[1] = F[2] = 0.0;
+        return;
+    }
+    double c[3];
+    cross(w, om, c);
+    const double s = 1.61 * d * d * sqrt(mu * rho_f / on);
+    for (int a = 0; a < 3; ++a) F[a] = s * c[a];
 }
 
 /* ---------------------------------------------------------------------------
@@ -762,8 +813,9 @@ void orc_diagnostics(const orc_params *p, const orc_state *s, orc_diag *out)
  *       Sec. 3.2.3 stability measures).
  *   S2  n_int interaction subcycles, each:
  *       (a) f_ext := eps_f f_b                   (external body force)
- *       (b) grad P  (lift and curl are not implemented)
- *       (c) F_am per particle, distributed to f_ext
+ *       (b) u_f and, with lift on, curl u_f (grad P depends on rho only
+ *           and is evaluated once per step)
+ *       (c) F_l (lift on) and F_am per particle, distributed to f_ext
  *       (d) re-evaluate u_f with the updated f_ext
  *       (e) F_pr, F_d per particle, F_d distributed; F_g (+ buoyancy)
  *       (f) accumulate f_ext / n_int for the LBM step
@@ -812,6 +864,9 @@ int orc_step(const orc_params *pin, orc_state *s, orc_aux *aux)
     double *facc = calloc(3 * (size_t)nc, sizeof(double));
     double *uf = malloc(sizeof(double) * 3 * (size_t)nc);
     double *epsp = malloc(sizeof(double) * (size_t)nc);
+    double *uf0 = malloc(sizeof(double) * 3 * (size_t)nc);
+    double *curl = calloc(3 * (size_t)nc, sizeof(double));
+    double *Fl = calloc(3 * (size_t)(np + 1), sizeof(double));
     double *Fam = calloc(3 * (size_t)(np + 1), sizeof(double));
     double *Fd = calloc(3 * (size_t)(np + 1), sizeof(double));
     double *Fpr = calloc(3 * (size_t)(np + 1), sizeof(double));
@@ -882,15 +937,33 @@ int orc_step(const orc_params *pin, orc_state *s, orc_aux *aux)
         }
         for (int64_t i = 0; i < np; ++i) particle_stencil(p, s->x + 3 * i, &st[i]);
 
-        /* (c) added mass, Table 1: F_am = C_am rho_f V (Du_f/Dt|p - du_p/dt),
+        /* (b) u_f = (j + f_ext/2) / (rho eps_f) at the subcycle start and its
+         *     lattice curl (Alg. 1 "Evaluate and store u_f, grad P, curl u_f") */
+        if (p->use_lift) {
+            for (int64_t c = 0; c < nc; ++c)
+                for (int a = 0; a < 3; ++a)
+                    uf0[a * nc + c] = (j[a * nc + c] + 0.5 * fext[a * nc + c]) / (rho[c] * eps[c]);
+            orc_curl_field(p, uf0, curl);
+        }
+
+        /* (c) lift (Table 1) from u_f and curl u_f of (b), and added mass,
+         *     F_am = C_am rho_f V (Du_f/Dt|p - du_p/dt); their sum is
          *     distributed with Eq. forces_pf (minus sign: reaction on the fluid) */
         for (int64_t i = 0; i < np; ++i) {
             double V = sphere_volume(s->d[i]);
-            double Du[3];
+            double Du[3], F1[3];
             interp(p, &st[i], dudt, 3, Du);
             for (int a = 0; a < 3; ++a)
                 Fam[3 * i + a] = p->use_am ? p->c_am * p->rho_f * V * (Du[a] - s->a[3 * i + a]) : 0.0;
-            spread(p, &st[i], fext, 3, Fam + 3 * i, -1.0);
+            if (p->use_lift) {
+                double om[3], ufp[3], w[3];
+                interp(p, &st[i], curl, 3, om);
+                interp(p, &st[i], uf0, 3, ufp);
+                for (int a = 0; a < 3; ++a) w[a] = ufp[a] - s->u[3 * i + a];
+                orc_lift(s->d[i], mu, p->rho_f, w, om, Fl + 3 * i);
+            }
+            for (int a = 0; a < 3; ++a) F1[a] = Fam[3 * i + a] + Fl[3 * i + a];
+            spread(p, &st[i], fext, 3, F1, -1.0);
         }
 
         /* (d) re-evaluate u_f = (j + f_ext/2) / (rho eps_f) */
@@ -914,7 +987,7 @@ int orc_step(const orc_params *pin, orc_state *s, orc_aux *aux)
             spread(p, &st[i], fext, 3, Fd + 3 * i, -1.0);
             for (int a = 0; a < 3; ++a) {
                 double fgb = (s->rho_p[i] - p->rho_f) * V * p->g[a];
-                Fc[3 * i + a] = Fd[3 * i + a] + Fpr[3 * i + a] + Fam[3 * i + a] + fgb;
+                Fc[3 * i + a] = Fd[3 * i + a] + Fpr[3 * i + a] + Fam[3 * i + a] + Fl[3 * i + a] + fgb;
                 imp_pr[a] += Fpr[3 * i + a] * dt_int;
                 imp_gb[a] += fgb * dt_int;
             }
@@ -985,6 +1058,8 @@ int orc_step(const orc_params *pin, orc_state *s, orc_aux *aux)
         if (aux->F_d) memcpy(aux->F_d, Fd, sizeof(double) * 3 * (size_t)np);
         if (aux->F_pr) memcpy(aux->F_pr, Fpr, sizeof(double) * 3 * (size_t)np);
         if (aux->F_const) memcpy(aux->F_const, Fc, sizeof(double) * 3 * (size_t)np);
+        if (aux->F_l) memcpy(aux->F_l, Fl, sizeof(double) * 3 * (size_t)np);
+        if (aux->curl) memcpy(aux->curl, curl, sizeof(double) * 3 * (size_t)nc);
         for (int a = 0; a < 3; ++a) {
             aux->impulse_pr[a] = imp_pr[a];
             aux->impulse_gb[a] = imp_gb[a];
@@ -996,7 +1071,7 @@ int orc_step(const orc_params *pin, orc_state *s, orc_aux *aux)
 
     free(rho); free(drho); free(j); free(eps); free(un); free(dudt); free(gradp);
     free(fext); free(facc); free(uf); free(epsp); free(Fam); free(Fd); free(Fpr);
-    free(Fc); free(Fdem); free(Tdem); free(ustart); free(st);
+    free(Fc); free(Fdem); free(Tdem); free(ustart); free(st); free(uf0); free(curl); free(Fl);
     return status;
 }
 

@@ -39,7 +39,7 @@ class Params(C.Structure):
                 ("h_c", C.c_double), ("h_min", C.c_double),
                 ("lub_stab", C.c_int32), ("use_lub", C.c_int32), ("use_am", C.c_int32),
                 ("n_int", C.c_int32), ("n_dem", C.c_int32),
-                ("c_am", C.c_double)]
+                ("c_am", C.c_double), ("use_lift", C.c_int32)]
 
 
 class State(C.Structure):
@@ -56,7 +56,7 @@ class Aux(C.Structure):
                 ("F_const", C.c_void_p),
                 ("impulse_pr", C.c_double * 3), ("impulse_gb", C.c_double * 3),
                 ("impulse_fb", C.c_double * 3), ("min_eps_f", C.c_double),
-                ("status", C.c_int32)]
+                ("status", C.c_int32), ("F_l", C.c_void_p), ("curl", C.c_void_p)]
 
 
 class Diag(C.Structure):
@@ -80,6 +80,8 @@ def lib():
         L.orc_drag_factor.restype = C.c_double
         L.orc_drag_factor.argtypes = [C.c_double, C.c_double]
         L.orc_drag.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p]
+        L.orc_lift.argtypes = [C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_curl_field.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p]
         L.orc_feq_dev.argtypes = [C.c_double, C.c_void_p, C.c_double, C.c_void_p]
         L.orc_guo.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_double, C.c_void_p]
         L.orc_moments.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -124,6 +126,7 @@ def make_params(prm) -> Params:
     P.lub_stab, P.use_lub, P.use_am = prm.lub_stab, prm.use_lub, prm.use_am
     P.n_int, P.n_dem = prm.n_int, prm.n_dem
     P.c_am = prm.c_am
+    P.use_lift = int(getattr(prm, "use_lift", 0))
     return P
 
 
@@ -201,7 +204,7 @@ class Oracle:
                 for k, shp in (("f_acc", (3, nc)), ("eps_f", (nc,)), ("dudt", (3, nc)),
                                ("gradp", (3, nc)), ("rho", (nc,)), ("j", (3, nc)),
                                ("F_am", (np_, 3)), ("F_d", (np_, 3)), ("F_pr", (np_, 3)),
-                               ("F_const", (np_, 3))):
+                               ("F_const", (np_, 3)), ("F_l", (np_, 3)), ("curl", (3, nc))):
                     keep[k] = np.zeros(shp)
                     setattr(A, k, _p(keep[k]))
             st = L.orc_step(C.byref(self.P), C.byref(S), C.byref(A))
@@ -268,6 +271,20 @@ def drag(d, mu, rho_f, eps, w):
     F = np.zeros(3)
     lib().orc_drag(float(d), float(mu), float(rho_f), float(eps), _p(np.asarray(w, np.float64)), _p(F))
     return F
+
+
+def lift(d, mu, rho_f, w, om):
+    F = np.zeros(3)
+    lib().orc_lift(float(d), float(mu), float(rho_f), _p(_v(w)), _p(_v(om)), _p(F))
+    return F
+
+
+def curl_field(P, u):
+    """Lattice curl of a [3][Nc] velocity field (Sec. 3.2.3), walls by the
+    ghost rule of the velocity gradient."""
+    out = np.zeros((3, P.n[0] * P.n[1] * P.n[2]))
+    lib().orc_curl_field(C.byref(P), _p(_v(u)), _p(out))
+    return out
 
 
 def collision_params(mij, e_n, T_c):

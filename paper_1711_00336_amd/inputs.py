@@ -87,6 +87,7 @@ class Params:
     c_am: float = 0.5
     use_lub: int = 1
     use_am: int = 1
+    use_lift: int = 0                       # shear-induced lift (Table 1)
     precision: str = "fp64"                 # "fp64" | "fp32dev"
     flags: int = 0                          # library flags (1: no graph replay)
 
