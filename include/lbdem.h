@@ -56,7 +56,9 @@ enum {
     LBDEM_FIELD_DUDT = 4,   /* Du_f/Dt of the last step (3) */
     LBDEM_FIELD_GRADP = 5,  /* grad P of the last step (3) */
     LBDEM_FIELD_UPREV = 6,  /* fluid-phase velocity kept for the next time derivative (3) */
-    LBDEM_FIELD_PDF = 7     /* f_q - w_q of the current state (19) */
+    LBDEM_FIELD_PDF = 7,    /* f_q - w_q of the current state (19) */
+    LBDEM_FIELD_CURL = 8    /* curl of u_f at the start of the last subcycle of
+                               the last step (3; only with use_lift, else E_STATE) */
 };
 
 /* Problem statement (Sec. 3.1, 3.2; Sec. 4.1 and 5.1 setups). */
@@ -86,6 +88,12 @@ typedef struct lbdem_params {
                                 as FP32 deviations from the rest weights; particle
                                 integration and reductions stay FP64) */
     uint32_t flags;          /* LBDEM_FLAG_* bits, 0 by default */
+    int32_t use_lift;        /* 1: shear-induced lift (Table 1, Saffman form)
+                                F_l = 1.61 d^2 sqrt(mu rho_f/|w_f|) ((u_f - u_p) x w_f),
+                                w_f the lattice curl of u_f (Sec. 3.2.3) interpolated
+                                to the particle; evaluated with the added mass from
+                                u_f at each subcycle start and spread with it
+                                (Alg. 1); F_l = 0 where w_f = 0. Default 0. */
 } lbdem_params;
 
 /* lbdem_params.flags: launch every kernel of a step directly instead of
@@ -163,9 +171,14 @@ lbdem_status lbdem_read_particles(lbdem_domain_t h, int mem_kind, double *x, dou
                                   double *omega, double *accel);
 
 /* Fluid-particle forces of the last subcycle [np][3] (NULL skips):
- * added mass, drag, pressure gradient, and their sum with gravity+buoyancy. */
+ * added mass, drag, pressure gradient, and their sum with gravity+buoyancy
+ * (and the lift when use_lift is set). */
 lbdem_status lbdem_read_particle_forces(lbdem_domain_t h, double *F_am, double *F_d,
                                         double *F_pr, double *F_const);
+
+/* Lift force of the last subcycle (Table 1), [np][3] host doubles in
+ * insertion order, caller-owned. E_STATE when the domain runs without lift. */
+lbdem_status lbdem_read_particle_lift(lbdem_domain_t h, double *F_l);
 
 /* FP64 reductions of the current state (Sec. 4.1 settling velocity). */
 lbdem_status lbdem_diagnostics(lbdem_domain_t h, lbdem_diag *out);
@@ -194,8 +207,8 @@ lbdem_status lbdem_load_state(lbdem_domain_t h, const void *blob, size_t size);
  * particle pass, 4 drag/pressure particle pass, 5 added-mass spreading,
  * 6 drag spreading and f_acc, 7 volume fraction (+ next added-mass
  * spreading), 8 Verlet list build, 9 DEM contact/lubrication forces,
- * 10 DEM integration, 11 particle binning and reordering.
- * E_INVALID for a class outside 0..11. */
+ * 10 DEM integration, 11 particle binning and reordering, 12 subcycle
+ * u_f and its curl (lift only). E_INVALID for a class outside 0..12. */
 lbdem_status lbdem_set_timing(lbdem_domain_t h, int on);
 lbdem_status lbdem_kernel_time(lbdem_domain_t h, int cls, double *ms_total, int64_t *launches);
 

@@ -63,6 +63,7 @@ struct lbdem_domain {
     int cur = 0;
     void *drho = nullptr, *j = nullptr, *uprev = nullptr, *un = nullptr, *dudt = nullptr, *gradp = nullptr;
     void *epsp = nullptr, *fam = nullptr, *uf = nullptr, *facc = nullptr;
+    void *curl = nullptr;       // lift only
     // bins
     int *cnt = nullptr, *start = nullptr, *list = nullptr, *bsum = nullptr, *loc = nullptr;
     int64_t list_cap = 0;
@@ -160,6 +161,7 @@ struct lbdem_domain {
         C.fam = (R *)fam;
         C.uf = (R *)uf;
         C.facc = (R *)facc;
+        C.curl = (R *)curl;
         return C;
     }
 
@@ -263,6 +265,7 @@ void resolve_phys(lbdem_domain_t h)
     P.lub_stab = p.lub_stab;
     P.use_lub = p.use_lub;
     P.use_am = p.use_am;
+    P.use_lift = p.use_lift ? 1 : 0;
     P.n_int = p.n_int;
     P.n_dem = p.n_dem;
     P.dt_int = 1.0 / p.n_int;
@@ -365,8 +368,15 @@ void rebuild(lbdem_domain_t h)
 void alloc_particles(lbdem_domain_t h, int64_t cap)
 {
     Parts &P = h->pt;
-    double **vec[] = {&P.x, &P.u, &P.w, &P.a, &P.x2, &P.u2, &P.w2, &P.a2, &P.Fam, &P.Fd, &P.Fpr, &P.Fc,
-                      &P.Fdem, &P.Tdem, &P.ustart, &P.xstart, &P.Fam_id, &P.Fd_id, &P.Fpr_id, &P.Fc_id};
+    std::vector<double **> vec = {&P.x, &P.u, &P.w, &P.a, &P.x2, &P.u2, &P.w2, &P.a2, &P.Fam, &P.Fd, &P.Fpr, &P.Fc,
+                                  &P.Fdem, &P.Tdem, &P.ustart, &P.xstart, &P.Fam_id, &P.Fd_id, &P.Fpr_id, &P.Fc_id};
+    h->dfree(P.Fl);
+    h->dfree(P.Fl_id);
+    P.Fl = P.Fl_id = nullptr;
+    if (h->phys.use_lift) {
+        vec.push_back(&P.Fl);
+        vec.push_back(&P.Fl_id);
+    }
     double **sca[] = {&P.d, &P.rho, &P.d2, &P.rho2};
     int **ints[] = {&P.id, &P.id2};
     for (double **v : vec) { h->dfree(*v); *v = nullptr; }
@@ -545,15 +555,19 @@ void check_particles(lbdem_domain_t h, int64_t n, const double *x, const double 
 
 // One coupled step, Alg. 1. The volume-fraction update that closes
 // subcycle k and the added-mass spreading that opens subcycle k+1 use the
-// same positions and bins, so they share one gather pass.
+// same positions and bins, so they share one gather pass. With lift, the
+// subcycle's u_f and curl need the new volume fraction first, so the two
+// passes run apart with the curl pass between them.
 template <typename R>
 void enqueue_step(lbdem_domain_t h)
 {
     hipStream_t s = h->stream;
     const Cells<R> C = h->cells<R>();
     const int nint = h->phys.n_int;
+    const bool lift = h->phys.use_lift != 0;
     launch_cls(h, 1, [&] { launch_moments<R>(h->desc(), C, s); });
     launch_cls(h, 2, [&] { launch_cellfields<R>(h->desc(), C, s); });
+    if (lift) launch_cls(h, 12, [&] { launch_curl<R>(h->desc(), C, s); });
     launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
     launch_cls(h, 5, [&] { launch_gather_am<R>(h->desc(), C, s); });
     for (int k = 0; k < nint; ++k) {
@@ -566,7 +580,12 @@ void enqueue_step(lbdem_domain_t h)
             launch_cls(h, 10, [&] { launch_integrate(h->desc(), sub == h->phys.n_dem - 1, s); });
         }
         launch_cls(h, 11, [&] { sort_particles(h); });
-        if (!last_sub) {
+        if (!last_sub && lift) {
+            launch_cls(h, 7, [&] { launch_gather_eps<R>(h->desc(), C, s); });
+            launch_cls(h, 12, [&] { launch_curl<R>(h->desc(), C, s); });
+            launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
+            launch_cls(h, 5, [&] { launch_gather_am<R>(h->desc(), C, s); });
+        } else if (!last_sub) {
             launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
             launch_cls(h, 7, [&] { launch_gather_eps_am<R>(h->desc(), C, s); });
         } else {
@@ -644,6 +663,10 @@ void read_field_impl(lbdem_domain_t h, int field, double *dev_out)
     case LBDEM_FIELD_GRADP: src = (const R *)h->gradp; ncomp = 3; break;
     case LBDEM_FIELD_UPREV: src = (const R *)h->uprev; ncomp = 3; break;
     case LBDEM_FIELD_PDF: src = (const R *)h->df[h->cur]; ncomp = 19; break;
+    case LBDEM_FIELD_CURL:
+        launch_vec4_to_double<R>((const R *)h->curl, dev_out, nc, h->stream);
+        hip_check(hipGetLastError(), "read_field");
+        return;
     default: throw std::runtime_error("unknown field id");
     }
     launch_to_double<R>(src, dev_out, ncomp * nc, h->stream);
@@ -751,6 +774,10 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
         h->fam = h->dalloc(rs * 3 * nc);
         h->uf = h->dalloc(rs * 3 * nc);
         h->facc = h->dalloc(rs * 3 * nc);
+        if (h->phys.use_lift) {
+            h->curl = h->dalloc(rs * 4 * nc);
+            hip_check(hipMemsetAsync(h->curl, 0, rs * 4 * nc, h->stream), "memset");
+        }
         h->cnt = (int *)h->dalloc(sizeof(int) * nc);
         h->start = (int *)h->dalloc(sizeof(int) * (nc + 1));
         h->bsum = (int *)h->dalloc(sizeof(int) * ((nc + kScanPerBlock - 1) / kScanPerBlock + 1));
@@ -864,7 +891,8 @@ lbdem_status lbdem_sync(lbdem_domain_t h)
 lbdem_status lbdem_read_field(lbdem_domain_t h, int field, int mem_kind, double *out)
 {
     if (!h || !out) return fail(h, LBDEM_E_INVALID, "null argument");
-    if (field < 0 || field > LBDEM_FIELD_PDF) return fail(h, LBDEM_E_INVALID, "unknown field");
+    if (field < 0 || field > LBDEM_FIELD_CURL) return fail(h, LBDEM_E_INVALID, "unknown field");
+    if (field == LBDEM_FIELD_CURL && !h->curl) return fail(h, LBDEM_E_STATE, "the curl is kept only with use_lift");
     return guarded(h, [&]() -> lbdem_status {
         const int64_t n = field_ncomp(field) * h->geo.nc;
         double *dst = mem_kind == LBDEM_MEM_DEVICE ? out : h->scratch(n);
@@ -910,6 +938,17 @@ lbdem_status lbdem_read_particle_forces(lbdem_domain_t h, double *F_am, double *
         download_vec(h, h->pt.Fd_id, F_d, n);
         download_vec(h, h->pt.Fpr_id, F_pr, n);
         download_vec(h, h->pt.Fc_id, F_const, n);
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_read_particle_lift(lbdem_domain_t h, double *F_l)
+{
+    if (!h) return fail(nullptr, LBDEM_E_INVALID, "null handle");
+    if (!h->pt.Fl_id) return fail(h, LBDEM_E_STATE, "the domain runs without lift");
+    return guarded(h, [&]() -> lbdem_status {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        download_vec(h, h->pt.Fl_id, F_l, h->pt.np);
         return LBDEM_OK;
     });
 }

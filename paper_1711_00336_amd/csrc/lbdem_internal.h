@@ -24,6 +24,7 @@ struct Phys {
     double g[3], fb[3];         // particle gravity, fluid body-force density
     double e_n, mu_c, T_c, h_c, h_min;
     int lub_stab, use_lub, use_am;
+    int use_lift;               // shear-induced lift with the lattice curl
     int n_int, n_dem;
     double dt_int, dt_dem, c_am;
     double kn_per_m, xi_per_m;  // k_n / m_ij and xi_n / m_ij from T_c and e_n
@@ -46,6 +47,7 @@ struct Cells {
     R *fam;                     // [3] -sum_p D F_am of the current subcycle
     R *uf;                      // [3] u_f re-evaluated with f_ext = eps_f f_b + fam
     R *facc;                    // [3] subcycle mean of f_ext
+    R *curl;                    // [nc][4] curl of u_f at the subcycle start as (x, y, z, 0) (lift only)
 };
 
 // 1-cell bins: particles sorted by the cell of their position.
@@ -88,6 +90,7 @@ struct Parts {
     double *Fdem, *Tdem;        // contact + lubrication force and torque of the substep
     double *ustart, *xstart;    // velocity / position at subcycle start
     double *Fam_id, *Fd_id, *Fpr_id, *Fc_id;  // last subcycle's forces by insertion index
+    double *Fl, *Fl_id;         // lift (slot order; last subcycle by insertion index), lift only
     // Verlet lists by insertion index: nlist[id*nbr + t], nnb[id] entries,
     // built from positions xbuild[3][cap] (by id); slot_of[id] = current slot
     int *nlist, *nnb, *slot_of;
@@ -120,7 +123,7 @@ enum : int {
     FLAG_NLIST = 16             // a particle has more list neighbours than the capacity nbr
 };
 
-constexpr int kTimingClasses = 12;  // kernel classes of lbdem_kernel_time
+constexpr int kTimingClasses = 13;  // kernel classes of lbdem_kernel_time
 
 constexpr int kBlock = 256;
 constexpr int kScanItems = 8;   // per thread in the block scan
@@ -129,6 +132,7 @@ constexpr int kScanPerBlock = kBlock * kScanItems;
 // -- launchers (lbdem_kernels.hip) -----------------------------------------
 template <typename R> void launch_moments(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_cellfields(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_curl(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_part_am(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_am(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, int record, hipStream_t s);

@@ -290,6 +290,53 @@ __global__ __launch_bounds__(kBlock) void k_cellfields(Desc D, Cells<R> C)
 }
 
 // ---------------------------------------------------------------------------
+// Lift only, at every subcycle start (Alg. 1, "Evaluate and store u_f,
+// grad P, curl u_f"; grad P depends on rho alone and comes from the per-step
+// pass): u_f = (j + eps_f f_b / 2) / (rho eps_f) with the current eps_f
+// (Eq. MacVel, u_f = u_bar/eps_f), kept in uf for the lift's u_f|p, and the
+// lattice curl of Sec. 3.2.3,
+//   curl u_f(x) = (1/c_s^2) sum_q w_q c_q x u_f(x + c_q),
+// neighbours beyond a wall by the velocity ghost rule above.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void subcycle_uf(const Desc &D, const Cells<R> &C, int64_t c, double u[3])
+{
+    const int64_t nc = D.g.nc;
+    const double e = 1.0 - (double)C.epsp[c];
+    const double rho = 1.0 + (double)C.drho[c];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) u[b] = ((double)C.j[b * nc + c] + 0.5 * (e * D.p.fb[b])) / (rho * e);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_curl(Desc D, Cells<R> C)
+{
+    const int64_t nc = D.g.nc;
+    const int64_t c = gidx();
+    if (c >= nc) return;
+    int i, j, k;
+    cell_coords(D.g, c, i, j, k);
+    double s[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 1; q < 19; ++q) {
+        double sg;
+        const int64_t nb = ghost(D.g, i, j, k, q, sg);
+        double u[3];
+        subcycle_uf<R>(D, C, nb, u);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) u[b] *= sg;
+        s[0] += WQ(q) * (CY(q) * u[2] - CZ(q) * u[1]);
+        s[1] += WQ(q) * (CZ(q) * u[0] - CX(q) * u[2]);
+        s[2] += WQ(q) * (CX(q) * u[1] - CY(q) * u[0]);
+    }
+    double u[3];
+    subcycle_uf<R>(D, C, c, u);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) C.uf[b * nc + c] = (R)u[b];
+    store_vec4(C.curl + 4 * c, (R)(3.0 * s[0]), (R)(3.0 * s[1]), (R)(3.0 * s[2]));
+}
+
+// ---------------------------------------------------------------------------
 // a4: added mass (Table 1): F_am = C_am rho_f V (Du_f/Dt|_p - du_p/dt), the
 // fluid derivative interpolated with Eq. interpolation. Also records the
 // subcycle-start velocity and position.
@@ -339,9 +386,33 @@ template <typename R> __device__ __forceinline__ void am_force(const Desc &D, in
     }
 }
 
-// interpolation sums and the added-mass force in the cell precision R
-// (FP32 in the FP32-deviation form); F_am is stored FP64
-template <typename R>
+// F_l = 1.61 d^2 sqrt(mu rho_f / |w_f|) ((u_f|p - u_p) x w_f) (Table 1, lift),
+// w_f = (curl u_f)|p; zero where w_f = 0 (the formula's limit). u_p and u_f
+// are those of the subcycle start.
+template <typename R> __device__ __forceinline__ void lift_force(const Desc &D, int64_t i, const R uf[3], const R om[3])
+{
+    const Parts &P = D.pt;
+    const int64_t cap = P.cap;
+    const R on = sqrt(om[0] * om[0] + om[1] * om[1] + om[2] * om[2]);
+    R F[3] = {(R)0, (R)0, (R)0};
+    if (on > (R)0) {
+        R w[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) w[b] = uf[b] - (R)P.u[b * cap + i];
+        const R d = (R)P.d[i];
+        const R s = (R)1.61 * d * d * sqrt((R)D.p.mu * (R)D.p.rho_f / on);
+        F[0] = s * (w[1] * om[2] - w[2] * om[1]);
+        F[1] = s * (w[2] * om[0] - w[0] * om[2]);
+        F[2] = s * (w[0] * om[1] - w[1] * om[0]);
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) P.Fl[b * cap + i] = (double)F[b];
+}
+
+// interpolation sums and the added-mass force (and with LIFT the lift from
+// the interpolated u_f and curl u_f) in the cell precision R (FP32 in the
+// FP32-deviation form); the forces are stored FP64
+template <typename R, bool LIFT>
 __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
 {
     const int64_t i = gidx();
@@ -351,6 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
     Stencil st;
     load_stencil<R>(P, i, st);
     R Du[3] = {(R)0, (R)0, (R)0};
+    R U[3] = {(R)0, (R)0, (R)0}, Om[3] = {(R)0, (R)0, (R)0};
 #pragma unroll 1
     for (int oz = 0; oz < 3; ++oz) {
         const int cz = stencil_coord(st.b[2], oz - 1, D.g.n[2], D.g.per[2]);
@@ -366,10 +438,20 @@ __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
                 load_vec4(C.dudt + 4 * cell, v);
 #pragma unroll
                 for (int b = 0; b < 3; ++b) Du[b] += w * v[b];
+                if (LIFT) {
+                    R o[3];
+                    load_vec4(C.curl + 4 * cell, o);
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        U[b] += w * C.uf[b * nc + cell];
+                        Om[b] += w * o[b];
+                    }
+                }
             }
         }
     }
     am_force<R>(D, i, Du);
+    if (LIFT) lift_force<R>(D, i, U, Om);
 }
 
 // ---------------------------------------------------------------------------
@@ -449,7 +531,7 @@ __device__ __forceinline__ void gather_cell(const Desc &D, int i, int j, int k, 
 // sums the particles of its own 3x3x3 bins from LDS, in the order
 // (dz, dy, dx, slot) whatever the tile shape. Tiles whose halo holds more
 // than KMAX particles fall back to the per-cell global gather.
-//   MODE_AM : fam  = -sum_p D F_am                    (Eq. forces_pf, added mass)
+//   MODE_AM : fam  = -sum_p D (F_am + F_l)            (Eq. forces_pf, added mass, lift)
 //   MODE_FD : facc += (eps_f f_b + fam - sum_p D F_d) / n_int   (mean f_ext)
 //   MODE_EPS: epsp = sum_p D V_p                      (Eq. fluid_volume_fraction)
 //   MODE_EPS_AM: both of the new positions: the volume fraction at the end of
@@ -476,6 +558,11 @@ __device__ __forceinline__ void gather_value(const Parts &P, int p, double *v)
         v[0] = F[p];
         v[1] = F[P.cap + p];
         v[2] = F[2 * P.cap + p];
+        if (MODE == MODE_AM && P.Fl) {  // lift, spread together with the added mass
+            v[0] += P.Fl[p];
+            v[1] += P.Fl[P.cap + p];
+            v[2] += P.Fl[2 * P.cap + p];
+        }
     }
 }
 
@@ -717,7 +804,8 @@ __device__ __forceinline__ void drag_forces(const Desc &D, int64_t i, const R uf
         const R Fd = fac * wv[b];
         const R fgb = (rp - rho_f) * V * (R)D.p.g[b];
         const R Fam = (R)P.Fam[b * cap + i];
-        const R Fc = Fd + Fpr + Fam + fgb;
+        const R Fl = P.Fl ? (R)P.Fl[b * cap + i] : (R)0;
+        const R Fc = Fd + Fpr + Fam + Fl + fgb;
         P.Fd[b * cap + i] = (double)Fd;
         P.Fc[b * cap + i] = (double)Fc;
         if (record) {
@@ -725,6 +813,7 @@ __device__ __forceinline__ void drag_forces(const Desc &D, int64_t i, const R uf
             P.Fd_id[b * cap + pid] = (double)Fd;
             P.Fpr_id[b * cap + pid] = (double)Fpr;
             P.Fc_id[b * cap + pid] = (double)Fc;
+            if (P.Fl_id) P.Fl_id[b * cap + pid] = (double)Fl;
         }
     }
 }
@@ -765,21 +854,22 @@ __global__ __launch_bounds__(kBlock) void k_part_drag(Desc D, Cells<R> C, int re
 }
 
 // ---------------------------------------------------------------------------
-// LDS-tiled particle pass (a6 drag/pressure/gravity; the template also
-// covers a4's added mass, which runs per particle). A workgroup owns the particles whose bins lie in a TX x TY x TZ tile of cells
+// LDS-tiled particle pass (a6 drag/pressure/gravity, and a4's added mass
+// with lift; without lift the added mass runs per particle). A workgroup owns the particles whose bins lie in a TX x TY x TZ tile of cells
 // (one contiguous slot range per x-row of bins). It loads the cell fields of
 // the tile widened by one cell (wrapped on periodic axes, clamped on walled
 // ones, as the per-particle stencil does) into LDS with coalesced loads, and
 // every particle interpolates from LDS. The arithmetic and its order are
 // those of k_part_am / k_part_drag, so the results are bit-identical.
 // ---------------------------------------------------------------------------
-enum { PASS_AM = 0, PASS_DRAG = 1 };
+enum { PASS_AM = 0, PASS_DRAG = 1, PASS_AML = 2 };
 
 template <typename R, int PASS, int TX, int TY, int TZ>
 __global__ __launch_bounds__(256) void k_part_tile(Desc D, Cells<R> C, int record)
 {
     constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2, NHC = HX * HY * HZ;
-    constexpr int NV = PASS == PASS_AM ? 3 : 7;  // Du/Dt | u_f, grad P, eps_p
+    // Du/Dt | u_f, grad P, eps_p | Du/Dt, u_f, curl u_f
+    constexpr int NV = PASS == PASS_AM ? 3 : (PASS == PASS_DRAG ? 7 : 9);
     constexpr int NR = TY * TZ;
     static_assert(NR <= 64, "rows of one tile are scanned by one wavefront");
     __shared__ R cv[NV][NHC];
@@ -827,6 +917,11 @@ __global__ __launch_bounds__(256) void k_part_tile(Desc D, Cells<R> C, int recor
             const int64_t cell = cidx(D.g, gx, gy, gz);
             if (PASS == PASS_AM) {
                 load_vec4(C.dudt + 4 * cell, v);
+            } else if (PASS == PASS_AML) {
+                load_vec4(C.dudt + 4 * cell, v);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) v[3 + b] = C.uf[b * nc + cell];
+                load_vec4(C.curl + 4 * cell, v + 6);
             } else {
 #pragma unroll
                 for (int b = 0; b < 3; ++b) {
@@ -875,6 +970,13 @@ __global__ __launch_bounds__(256) void k_part_tile(Desc D, Cells<R> C, int recor
                     if (PASS == PASS_AM) {
 #pragma unroll
                         for (int b = 0; b < 3; ++b) acc[b] += w * cv[b][hc];
+                    } else if (PASS == PASS_AML) {
+#pragma unroll
+                        for (int b = 0; b < 3; ++b) {
+                            acc[b] += w * cv[b][hc];
+                            acc[3 + b] += w * cv[3 + b][hc];
+                            acc[6 + b] += w * cv[6 + b][hc];
+                        }
                     } else {
 #pragma unroll
                         for (int b = 0; b < 3; ++b) {
@@ -886,8 +988,14 @@ __global__ __launch_bounds__(256) void k_part_tile(Desc D, Cells<R> C, int recor
                 }
             }
         }
-        if (PASS == PASS_AM) am_force<R>(D, i, acc);
-        else drag_forces<R>(D, i, acc, acc + 3, acc[6], record);
+        if (PASS == PASS_AM) {
+            am_force<R>(D, i, acc);
+        } else if (PASS == PASS_AML) {
+            am_force<R>(D, i, acc);
+            lift_force<R>(D, i, acc + 3, acc + 6);
+        } else {
+            drag_forces<R>(D, i, acc, acc + 3, acc[6], record);
+        }
     }
 }
 
@@ -1633,11 +1741,29 @@ template <typename R> void launch_cellfields(const Desc &D, const Cells<R> &C, h
 {
     hipLaunchKernelGGL(k_cellfields<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
 }
+template <typename R> void launch_curl(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_curl<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+}
 // added-mass pass: one thread per particle (its 3-component stencil reads
-// are cheap enough that LDS staging of the halo does not pay)
+// are cheap enough that LDS staging of the halo does not pay). With lift it
+// reads 9 components per stencil cell and uses LDS tiles (16x4x8 cells in
+// FP32, 16x4x4 in FP64 to stay within 64 KiB of LDS), or one thread per
+// particle under gather variant 3.
 template <typename R> void launch_part_am(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
-    if (D.pt.np > 0) hipLaunchKernelGGL(k_part_am<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
+    if (D.pt.np == 0) return;
+    if (!D.p.use_lift) {
+        hipLaunchKernelGGL((k_part_am<R, false>), dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
+        return;
+    }
+    if (D.t.gather == 3) {
+        hipLaunchKernelGGL((k_part_am<R, true>), dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
+        return;
+    }
+    constexpr int TZ = sizeof(R) == 4 ? 8 : 4;
+    dim3 grid((D.g.n[0] + 15) / 16, (D.g.n[1] + 3) / 4, (D.g.n[2] + TZ - 1) / TZ);
+    hipLaunchKernelGGL((k_part_tile<R, PASS_AML, 16, 4, TZ>), grid, dim3(256), 0, s, D, C, 0);
 }
 // gather variants (chosen per domain by the autotuner, else by particle
 // density): 0 tiles of 16x4x8 cells (two per thread, up to 256 staged
@@ -1785,6 +1911,7 @@ void launch_set_step(long long *stepc, long long v, hipStream_t s)
 #define LBDEM_INST(R)                                                                                     \
     template void launch_moments<R>(const Desc &, const Cells<R> &, hipStream_t);                          \
     template void launch_cellfields<R>(const Desc &, const Cells<R> &, hipStream_t);                       \
+    template void launch_curl<R>(const Desc &, const Cells<R> &, hipStream_t);                            \
     template void launch_part_am<R>(const Desc &, const Cells<R> &, hipStream_t);                          \
     template void launch_gather_am<R>(const Desc &, const Cells<R> &, hipStream_t);                        \
     template void launch_part_drag<R>(const Desc &, const Cells<R> &, int, hipStream_t);                        \

@@ -79,8 +79,9 @@ size_t footprint_of(const lbdem_params &p, int64_t np, double dmax)
     const size_t rs = p.precision == LBDEM_FP64 ? 8 : 4;
     const double reach = dmax + (p.use_lub ? std::max(p.h_c, 0.0) : 0.0) + 0.25;
     const double nbr = 2.0 * (double)np / (double)nc * (4.0 / 3.0) * M_PI * reach * reach * reach + 28.0;
-    const size_t per_particle = 1100 + 4 * (size_t)std::max(32.0, nbr);
-    return nc * (rs * (2 * 19 + 30) + 12) + (size_t)std::max<int64_t>(np, 64) * per_particle + (32u << 20);
+    const size_t per_particle = 1100 + (p.use_lift ? 48 : 0) + 4 * (size_t)std::max(32.0, nbr);
+    return nc * (rs * (2 * 19 + 30 + (p.use_lift ? 4 : 0)) + 12) + (size_t)std::max<int64_t>(np, 64) * per_particle +
+           (32u << 20);
 }
 
 void finish(lbdem_server_t s, uint64_t t, Req &r, lbdem_status st)

@@ -17,13 +17,14 @@ LIB_PATH = os.path.join(_HERE, "_lib", "liblbdem.so")
 OK, E_INVALID, E_OOM, E_UNSTABLE, E_DEVICE, E_BUSY, E_STATE = range(7)
 FP64, FP32_DEV = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
-FIELD_DRHO, FIELD_J, FIELD_EPS_F, FIELD_F_ACC, FIELD_DUDT, FIELD_GRADP, FIELD_UPREV, FIELD_PDF = range(8)
+(FIELD_DRHO, FIELD_J, FIELD_EPS_F, FIELD_F_ACC, FIELD_DUDT, FIELD_GRADP, FIELD_UPREV, FIELD_PDF,
+ FIELD_CURL) = range(9)
 FIELD_NCOMP = {FIELD_DRHO: 1, FIELD_J: 3, FIELD_EPS_F: 1, FIELD_F_ACC: 3, FIELD_DUDT: 3,
-               FIELD_GRADP: 3, FIELD_UPREV: 3, FIELD_PDF: 19}
+               FIELD_GRADP: 3, FIELD_UPREV: 3, FIELD_PDF: 19, FIELD_CURL: 3}
 FLAG_NO_GRAPH = 1
 KCLASS = {"stream_collide": 0, "moments": 1, "cellfields": 2, "part_am": 3, "part_drag": 4,
           "gather_am": 5, "gather_fd": 6, "gather_eps": 7, "nlist": 8, "dem_force": 9,
-          "integrate": 10, "bins": 11}
+          "integrate": 10, "bins": 11, "curl": 12}
 
 
 class LbdemError(RuntimeError):
@@ -41,7 +42,8 @@ class lbdem_params(C.Structure):
                 ("h_c", C.c_double), ("h_min", C.c_double),
                 ("lub_stab", C.c_int32), ("use_lub", C.c_int32), ("use_am", C.c_int32),
                 ("n_int", C.c_int32), ("n_dem", C.c_int32),
-                ("c_am", C.c_double), ("precision", C.c_int32), ("flags", C.c_uint32)]
+                ("c_am", C.c_double), ("precision", C.c_int32), ("flags", C.c_uint32),
+                ("use_lift", C.c_int32)]
 
 
 class lbdem_diag(C.Structure):
@@ -101,6 +103,7 @@ def lib():
             "lbdem_read_field": (st, [H, C.c_int, C.c_int, C.c_void_p]),
             "lbdem_read_particles": (st, [H, C.c_int] + [C.c_void_p] * 4),
             "lbdem_read_particle_forces": (st, [H] + [C.c_void_p] * 4),
+            "lbdem_read_particle_lift": (st, [H, C.c_void_p]),
             "lbdem_diagnostics": (st, [H, C.POINTER(lbdem_diag)]),
             "lbdem_num_cells": (C.c_int64, [H]),
             "lbdem_num_particles": (C.c_int64, [H]),
@@ -161,6 +164,7 @@ def params_from(prm) -> lbdem_params:
     P.c_am = prm.c_am
     P.precision = FP32_DEV if prm.precision == "fp32dev" else FP64
     P.flags = int(getattr(prm, "flags", 0))
+    P.use_lift = int(getattr(prm, "use_lift", 0))
     return P
 
 
@@ -243,6 +247,11 @@ class Domain:
         F = [np.zeros((n, 3)) for _ in range(4)]
         _check(self.h, lib().lbdem_read_particle_forces(self.h, *[_ptr(f) for f in F]))
         return dict(F_am=F[0], F_d=F[1], F_pr=F[2], F_const=F[3])
+
+    def lbdem_read_particle_lift(self):
+        F = np.zeros((self.num_particles(), 3))
+        _check(self.h, lib().lbdem_read_particle_lift(self.h, _ptr(F)))
+        return F
 
     def lbdem_diagnostics(self):
         D = lbdem_diag()
