@@ -109,11 +109,13 @@ def kernel_bytes(case, nlist):
                       u_prev, f_acc written                                 19 rs
       part_am         per particle stencil (9 weights, 3 ints), a, d, rho
                       read, F_am written; per cell Du/Dt read        140 B + 3 rs
+                      (with lift also u read, F_l written; per cell u_f
+                      and curl read                                  188 B + 9 rs)
       part_drag       per particle stencil, u, d, rho, F_am, id read,
                       F_d, F_const written; per cell u_f, grad P, eps_p
                       read                                           200 B + 7 rs
       gather_am       per cell eps_p, rho, j read, f_am, u_f written;
-                      per particle 9 weights + F_am                   11 rs + 96 B
+                      per particle 9 weights + F_am (+ F_l)   11 rs + 96 B (120 B)
       gather_fd       per cell eps_p, f_am, f_acc read, f_acc written;
                       per particle 9 weights + F_d                    10 rs + 96 B
       gather_eps      per cell rho, j read, eps_p, f_am, u_f written;
@@ -122,15 +124,18 @@ def kernel_bytes(case, nlist):
                       L list entries read, F, T written          140 B + 4 L B
       integrate       per particle x, u, omega, F_const, F, T, d, rho,
                       x_start read; x, u, omega written                 256 B
+      curl (lift)     per cell eps_p, rho, j read; u_f, curl written    11 rs
     """
     rs = 4 if case.params.precision == "fp32dev" else 8
     nc = int(np.prod(case.params.n))
     n = int(case.particles.n)
+    lift = bool(getattr(case.params, "use_lift", 0))
     return {"stream_collide": nc * 42 * rs, "moments": nc * 27 * rs, "cellfields": nc * 19 * rs,
-            "part_am": n * 140 + nc * 3 * rs, "part_drag": n * 200 + nc * 7 * rs,
-            "gather_am": nc * 11 * rs + n * 96, "gather_fd": nc * 10 * rs + n * 96,
+            "part_am": n * 188 + nc * 9 * rs if lift else n * 140 + nc * 3 * rs,
+            "part_drag": n * 200 + nc * 7 * rs,
+            "gather_am": nc * 11 * rs + n * (120 if lift else 96), "gather_fd": nc * 10 * rs + n * 96,
             "gather_eps": nc * 11 * rs + n * 104,
-            "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * 256}
+            "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * 256, "curl": nc * 11 * rs}
 
 
 PROFILES = os.path.join(ROOT, "profiles")
@@ -421,6 +426,7 @@ def main():
     ap.add_argument("--steps-hi", type=int, default=5000)
     ap.add_argument("--no-k10", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
+    ap.add_argument("--lift", action="store_true", help="shear-induced lift on (step mode)")
     args = ap.parse_args()
     dense = args.mode == "step" and args.workload == "dense"
     if args.steps is None:
@@ -447,6 +453,9 @@ def main():
     from paper_1711_00336_amd import lbdem
 
     case = workload(args.workload, args.seed)
+    if args.lift:
+        case.params = case.params.copy(use_lift=1)
+        case.name += "+lift"
     print(f"[bench] workload {case.name}: cells {np.prod(case.params.n)}, particles {case.particles.n}",
           file=sys.stderr, flush=True)
     torch.cuda.init()
@@ -499,6 +508,12 @@ def main():
                     v["ms_per_step"] for v in times.values()), 4)}
     if dom_cls == "dem_force":
         roofline["mean_list_length"] = round(nlist, 2)
+    roof_curl = None
+    if args.lift and times["curl"]["avg_launch_ms"] > 0:
+        a = kb["curl"] / (times["curl"]["avg_launch_ms"] * 1e-3) / 1e9
+        roof_curl = {"bound": "hbm", "kernel": "curl", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(a / HBM_PEAK_GBS, 4), "traffic": measured_traffic("curl", args.workload, variant),
+                     "bytes_per_launch": kb["curl"], "avg_launch_ms": round(times["curl"]["avg_launch_ms"], 5)}
     roof_k10 = None
     if not args.no_k10:
         print("[bench] stream-collide alone on the 256x256x512 grid", file=sys.stderr, flush=True)
@@ -536,9 +551,11 @@ def main():
         "config": {"workload": case.name, "cells": int(nc), "particles": int(case.particles.n),
                    "n_int": case.params.n_int, "n_dem": case.params.n_dem,
                    "pdf_storage": "f32 deviation" if case.params.precision == "fp32dev" else "f64 deviation",
-                   "particle_integration": "f64", "tau": case.params.tau, "gather_variant": variant},
+                   "particle_integration": "f64", "tau": case.params.tau, "gather_variant": variant,
+                   "lift": bool(args.lift)},
         "roofline": roofline,
         "roofline_stream_collide": roof_k10,
+        **({"roofline_curl": roof_curl} if args.lift else {}),
         "cpu_baseline": cpu,
         "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in times.items()},
         "u_ps": diag["u_ps"],

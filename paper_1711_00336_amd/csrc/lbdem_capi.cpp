@@ -581,7 +581,7 @@ void enqueue_step(lbdem_domain_t h)
         }
         launch_cls(h, 11, [&] { sort_particles(h); });
         if (!last_sub && lift) {
-            launch_cls(h, 7, [&] { launch_gather_eps<R>(h->desc(), C, s); });
+            launch_cls(h, 7, [&] { launch_gather_eps_uf<R>(h->desc(), C, s); });
             launch_cls(h, 12, [&] { launch_curl<R>(h->desc(), C, s); });
             launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
             launch_cls(h, 5, [&] { launch_gather_am<R>(h->desc(), C, s); });

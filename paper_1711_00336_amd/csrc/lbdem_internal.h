@@ -139,6 +139,7 @@ template <typename R> void launch_part_drag(const Desc &D, const Cells<R> &C, in
 template <typename R> void launch_gather_fd(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_gather_eps_am(const Desc &D, const Cells<R> &C, hipStream_t s);
+template <typename R> void launch_gather_eps_uf(const Desc &D, const Cells<R> &C, hipStream_t s);
 constexpr int kGatherVariants = 5;
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s);
 template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s);

@@ -206,32 +206,62 @@ __global__ __launch_bounds__(kBlock) void k_moments(Desc D, Cells<R> C)
     C.j[c] = jx;
     C.j[nc + c] = jy;
     C.j[2 * nc + c] = jz;
-    // fluid-phase velocity with the body force only (Eq. MacVel, u_f = u_bar/eps_f)
+    // fluid-phase velocity with the body force only (Eq. MacVel, u_f = u_bar/eps_f);
+    // with lift also the first subcycle's u_f, from which its curl is taken
     const double e = 1.0 - (double)C.epsp[c];
     const double rho = 1.0 + (double)r;
-    C.un[c] = (R)(((double)jx + 0.5 * e * D.p.fb[0]) / (rho * e));
-    C.un[nc + c] = (R)(((double)jy + 0.5 * e * D.p.fb[1]) / (rho * e));
-    C.un[2 * nc + c] = (R)(((double)jz + 0.5 * e * D.p.fb[2]) / (rho * e));
+    const R u0 = (R)(((double)jx + 0.5 * e * D.p.fb[0]) / (rho * e));
+    const R u1 = (R)(((double)jy + 0.5 * e * D.p.fb[1]) / (rho * e));
+    const R u2 = (R)(((double)jz + 0.5 * e * D.p.fb[2]) / (rho * e));
+    C.un[c] = u0;
+    C.un[nc + c] = u1;
+    C.un[2 * nc + c] = u2;
+    if (D.p.use_lift) {
+        C.uf[c] = u0;
+        C.uf[nc + c] = u1;
+        C.uf[2 * nc + c] = u2;
+    }
 }
 
-// neighbour x + c_q with the wall ghost rule: the mirrored in-domain cell;
+// Neighbours x + c_q with the wall ghost rule: the mirrored in-domain cell;
 // a velocity flips sign once per mirrored axis (no-slip at the half-way
-// plane), a scalar keeps its value.
-__device__ __forceinline__ int64_t ghost(const Geo &g, int i, int j, int k, int q, double &sign)
+// plane), a scalar keeps its value. Resolved once per cell and axis: o[a][d+1]
+// is the flat-index term of coordinate (i_a + d) (times 1, nx or nx*ny;
+// 32-bit, since a domain has fewer than 2^31 cells) and s[a][d+1] the sign a
+// velocity takes there.
+struct Nbh {
+    int o[3][3];
+    double s[3][3];
+};
+
+__device__ __forceinline__ void neighbourhood(const Geo &g, int i, int j, int k, Nbh &h)
 {
-    int t[3] = {i + CX(q), j + CY(q), k + CZ(q)};
-    sign = 1.0;
+    const int c[3] = {i, j, k};
+    const int stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (t[a] < 0 || t[a] >= g.n[a]) {
-            if (g.per[a]) t[a] = wrap1(t[a], g.n[a]);
-            else {
-                t[a] = t[a] < 0 ? 0 : g.n[a] - 1;
-                sign = -sign;
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int d = -1; d <= 1; ++d) {
+            int t = c[a] + d;
+            double sg = 1.0;
+            if (t < 0 || t >= g.n[a]) {
+                if (g.per[a]) t = wrap1(t, g.n[a]);
+                else {
+                    t = c[a];
+                    sg = -1.0;
+                }
             }
+            h.o[a][d + 1] = t * stride[a];
+            h.s[a][d + 1] = sg;
         }
-    }
-    return cidx(g, t[0], t[1], t[2]);
+}
+
+// flat index and velocity sign of neighbour x + c_q (q a compile-time constant
+// in unrolled loops, so the table lookups are register selects)
+__device__ __forceinline__ int ghost(const Nbh &h, int q, double &sign)
+{
+    sign = h.s[0][CX(q) + 1] * h.s[1][CY(q) + 1] * h.s[2][CZ(q) + 1];
+    return h.o[0][CX(q) + 1] + h.o[1][CY(q) + 1] + h.o[2][CZ(q) + 1];
 }
 
 // ---------------------------------------------------------------------------
@@ -249,12 +279,14 @@ __global__ __launch_bounds__(kBlock) void k_cellfields(Desc D, Cells<R> C)
     if (c >= nc) return;
     int i, j, k;
     cell_coords(D.g, c, i, j, k);
+    Nbh h;
+    neighbourhood(D.g, i, j, k, h);
     double G[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     double gp[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
         double sg;
-        const int64_t nb = ghost(D.g, i, j, k, q, sg);
+        const int64_t nb = ghost(h, q, sg);
         const double u0 = (double)C.un[nb];
         const double u1 = (double)C.un[nc + nb];
         const double u2 = (double)C.un[2 * nc + nb];
@@ -292,22 +324,12 @@ __global__ __launch_bounds__(kBlock) void k_cellfields(Desc D, Cells<R> C)
 // ---------------------------------------------------------------------------
 // Lift only, at every subcycle start (Alg. 1, "Evaluate and store u_f,
 // grad P, curl u_f"; grad P depends on rho alone and comes from the per-step
-// pass): u_f = (j + eps_f f_b / 2) / (rho eps_f) with the current eps_f
-// (Eq. MacVel, u_f = u_bar/eps_f), kept in uf for the lift's u_f|p, and the
-// lattice curl of Sec. 3.2.3,
+// pass): the lattice curl of Sec. 3.2.3,
 //   curl u_f(x) = (1/c_s^2) sum_q w_q c_q x u_f(x + c_q),
-// neighbours beyond a wall by the velocity ghost rule above.
+// of the subcycle-start u_f = (j + eps_f f_b / 2) / (rho eps_f) that the
+// moments pass (first subcycle) or the volume-fraction gather (later ones)
+// leaves in uf; neighbours beyond a wall by the velocity ghost rule above.
 // ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ void subcycle_uf(const Desc &D, const Cells<R> &C, int64_t c, double u[3])
-{
-    const int64_t nc = D.g.nc;
-    const double e = 1.0 - (double)C.epsp[c];
-    const double rho = 1.0 + (double)C.drho[c];
-#pragma unroll
-    for (int b = 0; b < 3; ++b) u[b] = ((double)C.j[b * nc + c] + 0.5 * (e * D.p.fb[b])) / (rho * e);
-}
-
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_curl(Desc D, Cells<R> C)
 {
@@ -316,23 +338,18 @@ __global__ __launch_bounds__(kBlock) void k_curl(Desc D, Cells<R> C)
     if (c >= nc) return;
     int i, j, k;
     cell_coords(D.g, c, i, j, k);
+    Nbh h;
+    neighbourhood(D.g, i, j, k, h);
     double s[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 1; q < 19; ++q) {
         double sg;
-        const int64_t nb = ghost(D.g, i, j, k, q, sg);
-        double u[3];
-        subcycle_uf<R>(D, C, nb, u);
-#pragma unroll
-        for (int b = 0; b < 3; ++b) u[b] *= sg;
-        s[0] += WQ(q) * (CY(q) * u[2] - CZ(q) * u[1]);
-        s[1] += WQ(q) * (CZ(q) * u[0] - CX(q) * u[2]);
-        s[2] += WQ(q) * (CX(q) * u[1] - CY(q) * u[0]);
+        const int64_t nb = ghost(h, q, sg);
+        const double u0 = sg * (double)C.uf[nb], u1 = sg * (double)C.uf[nc + nb], u2 = sg * (double)C.uf[2 * nc + nb];
+        s[0] += WQ(q) * (CY(q) * u2 - CZ(q) * u1);
+        s[1] += WQ(q) * (CZ(q) * u0 - CX(q) * u2);
+        s[2] += WQ(q) * (CX(q) * u1 - CY(q) * u0);
     }
-    double u[3];
-    subcycle_uf<R>(D, C, c, u);
-#pragma unroll
-    for (int b = 0; b < 3; ++b) C.uf[b * nc + c] = (R)u[b];
     store_vec4(C.curl + 4 * c, (R)(3.0 * s[0]), (R)(3.0 * s[1]), (R)(3.0 * s[2]));
 }
 
@@ -536,17 +553,21 @@ __device__ __forceinline__ void gather_cell(const Desc &D, int i, int j, int k, 
 //   MODE_EPS: epsp = sum_p D V_p                      (Eq. fluid_volume_fraction)
 //   MODE_EPS_AM: both of the new positions: the volume fraction at the end of
 //            one subcycle and the added-mass spreading of the next one
+//   MODE_EPS_UF: the volume fraction and, for the lift's curl, the next
+//            subcycle's starting u_f = (j + eps_f f_b/2) / (rho eps_f)
 // MODE_AM and MODE_EPS_AM also store the re-evaluated fluid-phase velocity
 // u_f = (j + (eps_f f_b + fam)/2) / (rho eps_f) (Sec. 3.2.3, Alg. 1).
 // ---------------------------------------------------------------------------
-enum { MODE_AM = 0, MODE_FD = 1, MODE_EPS = 2, MODE_EPS_AM = 3 };
+enum { MODE_AM = 0, MODE_FD = 1, MODE_EPS = 2, MODE_EPS_AM = 3, MODE_EPS_UF = 4 };
 
-template <int MODE> struct GatherNV { static constexpr int v = MODE == MODE_EPS ? 1 : (MODE == MODE_EPS_AM ? 4 : 3); };
+template <int MODE> struct GatherNV {
+    static constexpr int v = (MODE == MODE_EPS || MODE == MODE_EPS_UF) ? 1 : (MODE == MODE_EPS_AM ? 4 : 3);
+};
 
 template <int MODE>
 __device__ __forceinline__ void gather_value(const Parts &P, int p, double *v)
 {
-    if (MODE == MODE_EPS) {
+    if (MODE == MODE_EPS || MODE == MODE_EPS_UF) {
         v[0] = sphere_volume(P.d[p]);
     } else if (MODE == MODE_EPS_AM) {
         v[0] = sphere_volume(P.d[p]);
@@ -602,6 +623,13 @@ __device__ __forceinline__ void gather_store(const Desc &D, const Cells<R> &C, i
         const double e = 1.0 - s[0];
         if (!(e > 0.0) || !isfinite(e)) atomicOr(D.flags, FLAG_EPS);
         C.epsp[c] = (R)s[0];
+        if (MODE == MODE_EPS_UF) {
+            const double ef = 1.0 - (double)(R)s[0];
+            const double rho = 1.0 + (double)C.drho[c];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                C.uf[b * nc + c] = (R)(((double)C.j[b * nc + c] + 0.5 * ef * D.p.fb[b]) / (rho * ef));
+        }
     }
 }
 
@@ -1821,6 +1849,10 @@ template <typename R> void launch_gather_eps(const Desc &D, const Cells<R> &C, h
 {
     launch_gather<R, MODE_EPS>(D, C, s);
 }
+template <typename R> void launch_gather_eps_uf(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    launch_gather<R, MODE_EPS_UF>(D, C, s);
+}
 template <typename R> void launch_gather_eps_am(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
     launch_gather<R, MODE_EPS_AM>(D, C, s);
@@ -1918,6 +1950,7 @@ void launch_set_step(long long *stepc, long long v, hipStream_t s)
     template void launch_gather_fd<R>(const Desc &, const Cells<R> &, hipStream_t);                        \
     template void launch_gather_eps<R>(const Desc &, const Cells<R> &, hipStream_t);                       \
     template void launch_gather_eps_am<R>(const Desc &, const Cells<R> &, hipStream_t);                    \
+    template void launch_gather_eps_uf<R>(const Desc &, const Cells<R> &, hipStream_t);                    \
     template void launch_stream_collide<R>(const Desc &, const Cells<R> &, hipStream_t);                   \
     template void launch_zero<R>(R *, int64_t, hipStream_t);                                                \
     template void launch_to_double<R>(const R *, double *, int64_t, hipStream_t);                          \
