@@ -24,6 +24,9 @@
  *     restitution, rolling, antisymmetry).
  *   - Lattice curl and lift: pinned (closed-form curl of sinusoidal and
  *     wall-bounded linear fields; Saffman's lift in a linear shear).
+ *   - Per-cell relaxation time (Eilers, Smagorinsky): pinned (Einstein's
+ *     dilute limit; Smagorinsky's nu_t = (C_s dx)^2 |S| on Chapman-Enskog
+ *     non-equilibrium states; Poiseuille flow with the Eilers viscosity).
  *   - Du_f/Dt time discretisation, a_p lag, subcycle averaging of the fluid
  *     force, near-wall kernel renormalisation: parity unpinned against the
  *     paper (the paper does not fix them); checked by invariants only.
@@ -68,7 +71,7 @@ static int OPP(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
 typedef struct {
     int32_t n[3];
     int32_t periodic[3];
-    double tau;      /* BGK relaxation time (tau_e = tau: no Eilers, no LES) */
+    double tau;      /* BGK relaxation time of the pure fluid (tau_e = tau without Eilers and LES) */
     double rho_f;    /* fluid density used in the closures */
     double g[3];     /* gravitational acceleration, acting on the particles */
     double fb[3];    /* fluid body-force density f_b */
@@ -77,6 +80,7 @@ typedef struct {
     int32_t n_int, n_dem;
     double c_am;
     int32_t use_lift;  /* shear-induced lift (Table 1) on/off */
+    int32_t use_eilers, use_les;  /* per-cell tau_e: Eilers viscosity, Smagorinsky LES */
 } orc_params;
 
 typedef struct {
@@ -292,6 +296,45 @@ void orc_guo(const double u[3], double eps, const double f[3], double tau, doubl
     }
 }
 
+/* Per-cell relaxation time tau_e = tau_* + tau_t (Eq. tau_e; Alg. 1, the
+ * two steps before the GNS-LBM step), from the cell's solid fraction eps_p,
+ * density rho and PDF deviations df with their equilibrium feq:
+ *  - Eilers (Eq. visc_eilers, reading of the garbled denominator as
+ *    1 - eps_p/eps_cp, Eilers' form): mu_* = mu_0 (1 + 0.5 [mu] eps_p /
+ *    (1 - eps_p/eps_cp))^2, [mu] = 2.5, eps_cp = 0.64, and with Eq.
+ *    visc_tau_* tau_* = 1/2 + (tau - 1/2) mu_* / mu_0;
+ *  - Smagorinsky (Eqs. visc_turb, tau_t): nu_t = tau_t c_s^2 = (C_s dx)^2 S,
+ *    S = Qbar/(2 rho c_s^2 tau_e), Qbar = sqrt(2 sum Q_ab Q_ab),
+ *    Q_ab = sum_q c_qa c_qb (f_q - f_q^eq), C_s = 0.1, dx = 1. With
+ *    tau_e = tau_* + tau_t this is tau_t^2 + tau_* tau_t = C_s^2 Qbar/(2 rho c_s^4),
+ *    solved for its positive root. (The printed closed form carries 2 sqrt 2
+ *    where this root carries 2; the two agree when its Qbar is read as
+ *    sqrt(sum Q_ab Q_ab), without the factor 2 under the root: the reading
+ *    keeps the defining relation.) rho is the cell's density. */
+double orc_tau_e(const orc_params *p, double eps_p, double rho, const double df[19], const double feq[19])
+{
+    double ts = p->tau;
+    if (p->use_eilers) {
+        const double b = 1.0 + 0.5 * 2.5 * eps_p / (1.0 - eps_p / 0.64);
+        ts = 0.5 + (p->tau - 0.5) * b * b;
+    }
+    if (!p->use_les) return ts;
+    double Qm[3][3] = {{0}};
+    for (int q = 0; q < Q; ++q) {
+        const double neq = df[q] - feq[q];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Qm[a][b] += CV[q][a] * CV[q][b] * neq;
+    }
+    double qq = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) qq += Qm[a][b] * Qm[a][b];
+    const double Qbar = sqrt(2.0 * qq);
+    const double cs = 0.1, cs4 = 1.0 / 9.0;
+    const double rhs = cs * cs * Qbar / (2.0 * rho * cs4);
+    const double tt = 0.5 * (sqrt(ts * ts + 4.0 * rhs) - ts);
+    return ts + tt;
+}
+
 /* One GNS-LBM update (Eq. LBM_Equation): collide every cell with its own
  * eps_f and force density f_acc, then stream to x + c_q. The velocity in the
  * equilibrium and the forcing is Eq. MacVel, u = (j + f/2)/rho.
@@ -319,10 +362,11 @@ void orc_lbm_collide_stream(const orc_params *p, const double *df_in, double *df
                 }
                 double eps = eps_f ? eps_f[c] : 1.0;
                 orc_feq_dev(drho, u, eps, feq);
-                orc_guo(u, eps, fx, p->tau, F);
+                const double tau = orc_tau_e(p, 1.0 - eps, rho, f, feq);
+                orc_guo(u, eps, fx, tau, F);
                 int pos[3] = {i, jj, k};
                 for (int q = 0; q < Q; ++q) {
-                    double post = f[q] + (feq[q] - f[q]) / p->tau + F[q];
+                    double post = f[q] + (feq[q] - f[q]) / tau + F[q];
                     int t[3], wall = 0;
                     for (int a = 0; a < 3; ++a) {
                         t[a] = pos[a] + CV[q][a];

@@ -39,7 +39,8 @@ class Params(C.Structure):
                 ("h_c", C.c_double), ("h_min", C.c_double),
                 ("lub_stab", C.c_int32), ("use_lub", C.c_int32), ("use_am", C.c_int32),
                 ("n_int", C.c_int32), ("n_dem", C.c_int32),
-                ("c_am", C.c_double), ("use_lift", C.c_int32)]
+                ("c_am", C.c_double), ("use_lift", C.c_int32),
+                ("use_eilers", C.c_int32), ("use_les", C.c_int32)]
 
 
 class State(C.Structure):
@@ -82,6 +83,8 @@ def lib():
         L.orc_drag.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p]
         L.orc_lift.argtypes = [C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_curl_field.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p]
+        L.orc_tau_e.restype = C.c_double
+        L.orc_tau_e.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_void_p, C.c_void_p]
         L.orc_feq_dev.argtypes = [C.c_double, C.c_void_p, C.c_double, C.c_void_p]
         L.orc_guo.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_double, C.c_void_p]
         L.orc_moments.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -127,6 +130,8 @@ def make_params(prm) -> Params:
     P.n_int, P.n_dem = prm.n_int, prm.n_dem
     P.c_am = prm.c_am
     P.use_lift = int(getattr(prm, "use_lift", 0))
+    P.use_eilers = int(getattr(prm, "use_eilers", 0))
+    P.use_les = int(getattr(prm, "use_les", 0))
     return P
 
 
@@ -277,6 +282,11 @@ def lift(d, mu, rho_f, w, om):
     F = np.zeros(3)
     lib().orc_lift(float(d), float(mu), float(rho_f), _p(_v(w)), _p(_v(om)), _p(F))
     return F
+
+
+def tau_e(P, eps_p, rho, df, feq):
+    """Per-cell relaxation time of a cell state (Eilers and/or LES per P)."""
+    return lib().orc_tau_e(C.byref(P), float(eps_p), float(rho), _p(_v(df)), _p(_v(feq)))
 
 
 def curl_field(P, u):

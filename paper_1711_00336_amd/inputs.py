@@ -88,6 +88,8 @@ class Params:
     use_lub: int = 1
     use_am: int = 1
     use_lift: int = 0                       # shear-induced lift (Table 1)
+    use_eilers: int = 0                     # Eilers viscosity of the suspension in tau_e
+    use_les: int = 0                        # Smagorinsky subgrid viscosity in tau_e
     precision: str = "fp64"                 # "fp64" | "fp32dev"
     flags: int = 0                          # library flags (1: no graph replay)
 
