@@ -168,13 +168,15 @@ def measured_traffic(kernel_class, workload_name, gather_variant=None):
         return None
 
 
-def k10_roofline(lbdem, stream, steps=10, warmup=3):
+def k10_roofline(lbdem, stream, steps=10, warmup=3, visc=False):
     """Fused stream-collide alone on the dense-suspension grid (256 x 256 x 512
     cells, walls in z, FP32 deviations): 2 x 2.55 GB of PDFs per step, far
     beyond the last-level cache, so its time is HBM time. No particles: the
-    kernel does the same work per cell with eps_f = 1 and f_acc = 0."""
+    kernel does the same work per cell with eps_f = 1 and f_acc = 0. visc:
+    the per-cell relaxation time (Eilers + Smagorinsky) variant, same bytes."""
     from paper_1711_00336_amd import inputs as I
-    prm = I.Params(n=(256, 256, 512), periodic=(1, 1, 0), tau=0.7, precision="fp32dev")
+    prm = I.Params(n=(256, 256, 512), periodic=(1, 1, 0), tau=0.7, precision="fp32dev",
+                   use_eilers=int(visc), use_les=int(visc))
     dom = lbdem.Domain(prm, stream=stream.cuda_stream)
     try:
         dom.lbdem_step(warmup)
@@ -190,10 +192,11 @@ def k10_roofline(lbdem, stream, steps=10, warmup=3):
     byts = nc * 42 * 4
     avg = ms / n
     ach = byts / (avg * 1e-3) / 1e9
-    return {"bound": "hbm", "kernel": "stream_collide", "workload": "fluid-256x256x512-fp32dev",
+    return {"bound": "hbm", "kernel": "stream_collide",
+            "workload": "fluid-256x256x512-fp32dev" + ("-eilers-les" if visc else ""),
             "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("stream_collide", "fluid-256x256x512"),
+            "traffic": measured_traffic("stream_collide", "fluid-256x256x512" + ("-eilers-les" if visc else "")),
             "bytes_per_launch": byts, "avg_launch_ms": round(avg, 5)}
 
 
@@ -427,6 +430,8 @@ def main():
     ap.add_argument("--no-k10", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     ap.add_argument("--lift", action="store_true", help="shear-induced lift on (step mode)")
+    ap.add_argument("--visc", action="store_true",
+                    help="per-cell relaxation time: Eilers viscosity and Smagorinsky LES (step and k10 modes)")
     args = ap.parse_args()
     dense = args.mode == "step" and args.workload == "dense"
     if args.steps is None:
@@ -445,8 +450,8 @@ def main():
         import torch
         from paper_1711_00336_amd import lbdem
         torch.cuda.init()
-        print(json.dumps({"mode": "k10", "roofline_stream_collide": k10_roofline(lbdem, torch.cuda.current_stream())}),
-              flush=True)
+        print(json.dumps({"mode": "k10", "roofline_stream_collide": k10_roofline(lbdem, torch.cuda.current_stream(),
+                                                                                 visc=args.visc)}), flush=True)
         return
 
     import torch
@@ -456,6 +461,9 @@ def main():
     if args.lift:
         case.params = case.params.copy(use_lift=1)
         case.name += "+lift"
+    if args.visc:
+        case.params = case.params.copy(use_eilers=1, use_les=1)
+        case.name += "+eilers+les"
     print(f"[bench] workload {case.name}: cells {np.prod(case.params.n)}, particles {case.particles.n}",
           file=sys.stderr, flush=True)
     torch.cuda.init()
@@ -517,7 +525,7 @@ def main():
     roof_k10 = None
     if not args.no_k10:
         print("[bench] stream-collide alone on the 256x256x512 grid", file=sys.stderr, flush=True)
-        roof_k10 = k10_roofline(lbdem, stream)
+        roof_k10 = k10_roofline(lbdem, stream, visc=args.visc)
     if args.calib_copy_mib > 0:
         # a plain device copy of known size, for scaling the HBM byte counters
         nb = args.calib_copy_mib << 20
@@ -552,7 +560,7 @@ def main():
                    "n_int": case.params.n_int, "n_dem": case.params.n_dem,
                    "pdf_storage": "f32 deviation" if case.params.precision == "fp32dev" else "f64 deviation",
                    "particle_integration": "f64", "tau": case.params.tau, "gather_variant": variant,
-                   "lift": bool(args.lift)},
+                   "lift": bool(args.lift), "eilers_les": bool(args.visc)},
         "roofline": roofline,
         "roofline_stream_collide": roof_k10,
         **({"roofline_curl": roof_curl} if args.lift else {}),

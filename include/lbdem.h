@@ -94,6 +94,16 @@ typedef struct lbdem_params {
                                 to the particle; evaluated with the added mass from
                                 u_f at each subcycle start and spread with it
                                 (Alg. 1); F_l = 0 where w_f = 0. Default 0. */
+    int32_t use_eilers;      /* 1: per-cell relaxation time from the Eilers
+                                suspension viscosity (Eq. visc_eilers, read with
+                                the denominator 1 - eps_p/eps_cp; [mu] = 2.5,
+                                eps_cp = 0.64) via Eq. visc_tau_*. Default 0. */
+    int32_t use_les;         /* 1: add the Smagorinsky subgrid relaxation time
+                                (Eqs. visc_turb, tau_t; C_s = 0.1) from the
+                                non-equilibrium momentum flux. Default 0.
+                                With either flag, tau_e replaces tau in the
+                                collision and in the forcing prefactor; tau
+                                stays the pure-fluid value of the closures. */
 } lbdem_params;
 
 /* lbdem_params.flags: launch every kernel of a step directly instead of

@@ -266,6 +266,8 @@ void resolve_phys(lbdem_domain_t h)
     P.use_lub = p.use_lub;
     P.use_am = p.use_am;
     P.use_lift = p.use_lift ? 1 : 0;
+    P.use_eilers = p.use_eilers ? 1 : 0;
+    P.use_les = p.use_les ? 1 : 0;
     P.n_int = p.n_int;
     P.n_dem = p.n_dem;
     P.dt_int = 1.0 / p.n_int;

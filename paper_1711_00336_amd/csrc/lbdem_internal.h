@@ -25,6 +25,7 @@ struct Phys {
     double e_n, mu_c, T_c, h_c, h_min;
     int lub_stab, use_lub, use_am;
     int use_lift;               // shear-induced lift with the lattice curl
+    int use_eilers, use_les;    // per-cell tau_e: Eilers viscosity, Smagorinsky LES
     int n_int, n_dem;
     double dt_int, dt_dem, c_am;
     double kn_per_m, xi_per_m;  // k_n / m_ij and xi_n / m_ij from T_c and e_n

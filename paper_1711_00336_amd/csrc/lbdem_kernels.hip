@@ -1568,7 +1568,45 @@ __global__ __launch_bounds__(kBlock) void k_permute(Desc D)
 // ---------------------------------------------------------------------------
 // GNS-BGK collision with Guo forcing of one cell (the post-collision values
 // of all 19 directions, before streaming)
+// Per-cell relaxation time tau_e = tau_* + tau_t (Eq. tau_e; Alg. 1, before
+// the GNS-LBM step), in the storage precision R:
+//  - Eilers (Eq. visc_eilers with the denominator 1 - eps_p/eps_cp of Eilers'
+//    form; [mu] = 2.5, eps_cp = 0.64) through Eq. visc_tau_*:
+//    tau_* = 1/2 + (tau - 1/2) (1 + 1.25 eps_p/(1 - eps_p/0.64))^2;
+//  - Smagorinsky (Eq. visc_turb, C_s = 0.1, dx = 1): tau_t is the positive
+//    root of tau_t^2 + tau_* tau_t = C_s^2 Qbar/(2 rho c_s^4), Qbar =
+//    sqrt(2 sum Q_ab Q_ab), Q_ab = sum_q c_qa c_qb (f_q - f_q^eq).
 template <typename R>
+__device__ __forceinline__ R relax_time(const Desc &D, R ep, R rho, const R f[19], const R feq[19])
+{
+    const R one = (R)1;
+    R tau = (R)D.p.tau;
+    if (D.p.use_eilers) {
+        const R b = one + (R)1.25 * ep / (one - ep / (R)0.64);
+        tau = (R)0.5 + ((R)D.p.tau - (R)0.5) * b * b;
+    }
+    if (D.p.use_les) {
+        R qxx = 0, qyy = 0, qzz = 0, qxy = 0, qxz = 0, qyz = 0;
+#pragma unroll
+        for (int q = 1; q < 19; ++q) {
+            const R n = f[q] - feq[q];
+            if (CX(q) != 0) qxx += n;
+            if (CY(q) != 0) qyy += n;
+            if (CZ(q) != 0) qzz += n;
+            if (CX(q) * CY(q) > 0) qxy += n; else if (CX(q) * CY(q) < 0) qxy -= n;
+            if (CX(q) * CZ(q) > 0) qxz += n; else if (CX(q) * CZ(q) < 0) qxz -= n;
+            if (CY(q) * CZ(q) > 0) qyz += n; else if (CY(q) * CZ(q) < 0) qyz -= n;
+        }
+        const R qq = qxx * qxx + qyy * qyy + qzz * qzz + (R)2 * (qxy * qxy + qxz * qxz + qyz * qyz);
+        const R qbar = sqrt((R)2 * qq);
+        // C_s^2 Qbar / (2 rho c_s^4) with C_s^2 = 0.01, 1/c_s^4 = 9
+        const R rhs = (R)0.045 * qbar / rho;
+        tau += (R)0.5 * (sqrt(tau * tau + (R)4 * rhs) - tau);
+    }
+    return tau;
+}
+
+template <typename R, bool VISC>
 __device__ __forceinline__ void collide_cell(const Desc &D, const Cells<R> &C, int64_t c, R post[19])
 {
     const int64_t nc = D.g.nc;
@@ -1591,6 +1629,29 @@ __device__ __forceinline__ void collide_cell(const Desc &D, const Cells<R> &C, i
     const R eps = one - C.epsp[c];
     const R ieps = one / eps;
     const R uu = ux * ux + uy * uy + uz * uz;
+    if (VISC) {
+        R feq[19];
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            const R cu = (R)CX(q) * ux + (R)CY(q) * uy + (R)CZ(q) * uz;
+            const R w = (R)WQ(q);
+            feq[q] = w * r + w * rho * ((R)3 * cu + (R)4.5 * cu * cu * ieps - (R)1.5 * uu * ieps);
+        }
+        const R tau = relax_time<R>(D, C.epsp[c], rho, f, feq);
+        const R om = one / tau;
+        const R pre = one - half / tau;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) {
+            const R cu = (R)CX(q) * ux + (R)CY(q) * uy + (R)CZ(q) * uz;
+            const R w = (R)WQ(q);
+            const R gx = (R)3 * (R)CX(q) - (R)3 * ux * ieps + (R)9 * cu * (R)CX(q) * ieps;
+            const R gy = (R)3 * (R)CY(q) - (R)3 * uy * ieps + (R)9 * cu * (R)CY(q) * ieps;
+            const R gz = (R)3 * (R)CZ(q) - (R)3 * uz * ieps + (R)9 * cu * (R)CZ(q) * ieps;
+            const R F = w * pre * (gx * fx + gy * fy + gz * fz);
+            post[q] = f[q] + (feq[q] - f[q]) * om + F;
+        }
+        return;
+    }
     const R om = (R)D.p.omega;
     const R pre = (R)(1.0 - 0.5 / D.p.tau);
 #pragma unroll
@@ -1609,7 +1670,7 @@ __device__ __forceinline__ void collide_cell(const Desc &D, const Cells<R> &C, i
 // push streaming: direction q of cell (i, j, k) goes to (i, j, k) + c_q,
 // wrapped on periodic axes; where it would leave through a wall it returns
 // into the opposite direction of the same cell (half-way bounce-back)
-template <typename R>
+template <typename R, bool VISC>
 __global__ __launch_bounds__(kBlock) void k_stream_collide(Desc D, Cells<R> C)
 {
     const int64_t nc = D.g.nc;
@@ -1619,7 +1680,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(Desc D, Cells<R> C)
     int i, j, k;
     cell_coords(D.g, c, i, j, k);
     R post[19];
-    collide_cell<R>(D, C, c, post);
+    collide_cell<R, VISC>(D, C, c, post);
     const bool wall_x = !D.g.per[0], wall_y = !D.g.per[1], wall_z = !D.g.per[2];
 #pragma unroll
     for (int q = 0; q < 19; ++q) {
@@ -1857,9 +1918,14 @@ template <typename R> void launch_gather_eps_am(const Desc &D, const Cells<R> &C
 {
     launch_gather<R, MODE_EPS_AM>(D, C, s);
 }
+// the per-cell relaxation time (Eilers, LES) is a separate instance so that
+// the constant-tau kernel keeps its code
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stream_collide<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+    if (D.p.use_eilers || D.p.use_les)
+        hipLaunchKernelGGL((k_stream_collide<R, true>), dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+    else
+        hipLaunchKernelGGL((k_stream_collide<R, false>), dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
 }
 template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s)
 {

@@ -43,7 +43,7 @@ class lbdem_params(C.Structure):
                 ("lub_stab", C.c_int32), ("use_lub", C.c_int32), ("use_am", C.c_int32),
                 ("n_int", C.c_int32), ("n_dem", C.c_int32),
                 ("c_am", C.c_double), ("precision", C.c_int32), ("flags", C.c_uint32),
-                ("use_lift", C.c_int32)]
+                ("use_lift", C.c_int32), ("use_eilers", C.c_int32), ("use_les", C.c_int32)]
 
 
 class lbdem_diag(C.Structure):
@@ -165,6 +165,8 @@ def params_from(prm) -> lbdem_params:
     P.precision = FP32_DEV if prm.precision == "fp32dev" else FP64
     P.flags = int(getattr(prm, "flags", 0))
     P.use_lift = int(getattr(prm, "use_lift", 0))
+    P.use_eilers = int(getattr(prm, "use_eilers", 0))
+    P.use_les = int(getattr(prm, "use_les", 0))
     return P
 
 
