@@ -1918,14 +1918,21 @@ template <typename R> void launch_gather_eps_am(const Desc &D, const Cells<R> &C
 {
     launch_gather<R, MODE_EPS_AM>(D, C, s);
 }
-// the per-cell relaxation time (Eilers, LES) is a separate instance so that
-// the constant-tau kernel keeps its code
+// The per-cell relaxation time (Eilers, LES) is a separate instance so that
+// the constant-tau kernel keeps its code.
+// Residency cap: the FP32 instances need few registers and would run 5 or 8
+// waves per SIMD. Reserving 40,000 B of (unused) dynamic LDS per 256-thread
+// workgroup limits a CU (160 KiB of LDS) to 4 workgroups, 4 waves per SIMD,
+// which is fastest for this kernel's 38 PDF streams: on 256 x 256 x 512
+// cells 8 waves/SIMD take 1.175 ms, 6 1.15 ms, 5 1.14 ms, 4 1.125 ms and
+// 3 1.33 ms. The FP64 instances already run at 4 and 3 waves per SIMD.
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
+    constexpr unsigned lds = sizeof(R) == 4 ? 40000u : 0u;
     if (D.p.use_eilers || D.p.use_les)
-        hipLaunchKernelGGL((k_stream_collide<R, true>), dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+        hipLaunchKernelGGL((k_stream_collide<R, true>), dim3(nblocks(D.g.nc)), dim3(kBlock), lds, s, D, C);
     else
-        hipLaunchKernelGGL((k_stream_collide<R, false>), dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+        hipLaunchKernelGGL((k_stream_collide<R, false>), dim3(nblocks(D.g.nc)), dim3(kBlock), lds, s, D, C);
 }
 template <typename R> void launch_zero(R *p, int64_t n, hipStream_t s)
 {
