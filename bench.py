@@ -124,7 +124,9 @@ def kernel_bytes(case, nlist):
                       L list entries read, F, T written          140 B + 4 L B
       integrate       per particle x, u, omega, F_const, F, T, d, rho,
                       x_start read; x, u, omega written                 256 B
-      curl (lift)     per cell eps_p, rho, j read; u_f, curl written    11 rs
+      curl (lift)     per cell u_f read, curl written (the subcycle's u_f is
+                      evaluated by the moments pass and the volume-fraction
+                      gather)                                            6 rs
     """
     rs = 4 if case.params.precision == "fp32dev" else 8
     nc = int(np.prod(case.params.n))
@@ -135,7 +137,7 @@ def kernel_bytes(case, nlist):
             "part_drag": n * 200 + nc * 7 * rs,
             "gather_am": nc * 11 * rs + n * (120 if lift else 96), "gather_fd": nc * 10 * rs + n * 96,
             "gather_eps": nc * 11 * rs + n * 104,
-            "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * 256, "curl": nc * 11 * rs}
+            "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * 256, "curl": nc * 6 * rs}
 
 
 PROFILES = os.path.join(ROOT, "profiles")
