@@ -349,6 +349,15 @@ void sort_particles(lbdem_domain_t h)
     swap_particle_buffers(h);
 }
 
+// the same, and the next subcycle's added-mass force of every particle
+template <typename R>
+void sort_particles_am(lbdem_domain_t h)
+{
+    launch_bin_build(h->desc(), h->stream);
+    launch_sort_permute_am<R>(h->desc(), h->cells<R>(), h->stream);
+    swap_particle_buffers(h);
+}
+
 template <typename R>
 void rebuild_particle_fields(lbdem_domain_t h)
 {
@@ -581,14 +590,16 @@ void enqueue_step(lbdem_domain_t h)
             launch_cls(h, 9, [&] { launch_dem_force(h->desc(), s); });
             launch_cls(h, 10, [&] { launch_integrate(h->desc(), sub == h->phys.n_dem - 1, s); });
         }
-        launch_cls(h, 11, [&] { sort_particles(h); });
+        // without lift the next subcycle's added mass is evaluated in the
+        // reordering pass, which holds every particle's new stencil
+        if (!last_sub && !lift) launch_cls(h, 11, [&] { sort_particles_am<R>(h); });
+        else launch_cls(h, 11, [&] { sort_particles(h); });
         if (!last_sub && lift) {
             launch_cls(h, 7, [&] { launch_gather_eps_uf<R>(h->desc(), C, s); });
             launch_cls(h, 12, [&] { launch_curl<R>(h->desc(), C, s); });
             launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
             launch_cls(h, 5, [&] { launch_gather_am<R>(h->desc(), C, s); });
         } else if (!last_sub) {
-            launch_cls(h, 3, [&] { launch_part_am<R>(h->desc(), C, s); });
             launch_cls(h, 7, [&] { launch_gather_eps_am<R>(h->desc(), C, s); });
         } else {
             launch_cls(h, 7, [&] { launch_gather_eps<R>(h->desc(), C, s); });

@@ -159,6 +159,8 @@ void launch_integrate(const Desc &D, int last_substep, hipStream_t s);
 void launch_bin_count(const Desc &D, hipStream_t s);
 void launch_bin_build(const Desc &D, hipStream_t s);   // scan + place
 void launch_sort_permute(const Desc &D, hipStream_t s); // order bins, slots <- bin order, stencils
+// the same, with the next subcycle's added-mass force evaluated in the permutation
+template <typename R> void launch_sort_permute_am(const Desc &D, const Cells<R> &C, hipStream_t s);
 void launch_zero_int(int *p, int64_t n, hipStream_t s);
 void launch_set_step(long long *stepc, long long v, hipStream_t s);
 void launch_set_int(int *p, int v, hipStream_t s);

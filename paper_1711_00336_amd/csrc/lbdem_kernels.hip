@@ -387,19 +387,63 @@ template <typename R> __device__ __forceinline__ void load_stencil(const Parts &
 // st.w[a][o] for a runtime o without indexing a register array
 __device__ __forceinline__ double sel3(const double w[3], int o) { return o == 0 ? w[0] : (o == 1 ? w[1] : w[2]); }
 
-// F_am = C_am rho_f V (Du/Dt|p - a_p) (Table 1); subcycle start state
+// F_am = C_am rho_f V (Du/Dt|p - a_p) (Table 1) of slot i from the particle's
+// diameter, du_p/dt, velocity and position; records the subcycle-start
+// velocity and position
+template <typename R>
+__device__ __forceinline__ void am_store(const Desc &D, int64_t i, const R Du[3], double d, const double a[3],
+                                         const double u[3], const double x[3])
+{
+    const Parts &P = D.pt;
+    const int64_t cap = P.cap;
+    const R V = (R)sphere_volume(d);
+    const R cam = (R)(D.p.c_am * D.p.rho_f);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const R F = D.p.use_am ? cam * V * (Du[b] - (R)a[b]) : (R)0;
+        P.Fam[b * cap + i] = (double)F;
+        P.ustart[b * cap + i] = u[b];
+        P.xstart[b * cap + i] = x[b];
+    }
+}
+
+// the same for the particle in slot i (subcycle start state)
 template <typename R> __device__ __forceinline__ void am_force(const Desc &D, int64_t i, const R Du[3])
 {
     const Parts &P = D.pt;
     const int64_t cap = P.cap;
-    const R V = (R)sphere_volume(P.d[i]);
-    const R cam = (R)(D.p.c_am * D.p.rho_f);
+    double a[3], u[3], x[3];
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-        const R F = D.p.use_am ? cam * V * (Du[b] - (R)P.a[b * cap + i]) : (R)0;
-        P.Fam[b * cap + i] = (double)F;
-        P.ustart[b * cap + i] = P.u[b * cap + i];
-        P.xstart[b * cap + i] = P.x[b * cap + i];
+        a[b] = P.a[b * cap + i];
+        u[b] = P.u[b * cap + i];
+        x[b] = P.x[b * cap + i];
+    }
+    am_store<R>(D, i, Du, P.d[i], a, u, x);
+}
+
+// Du_f/Dt|p = sum of the 27 stencil cells' Du_f/Dt with the stored weights
+// (Eq. interpolation), summed in R in the order (z, y, x)
+template <typename R>
+__device__ __forceinline__ void interp_dudt(const Desc &D, const Cells<R> &C, const Stencil &st, R Du[3])
+{
+#pragma unroll 1
+    for (int oz = 0; oz < 3; ++oz) {
+        const int cz = stencil_coord(st.b[2], oz - 1, D.g.n[2], D.g.per[2]);
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+            const int cy = stencil_coord(st.b[1], oy - 1, D.g.n[1], D.g.per[1]);
+#pragma unroll
+            for (int ox = 0; ox < 3; ++ox) {
+                const int cx = stencil_coord(st.b[0], ox - 1, D.g.n[0], D.g.per[0]);
+                const int64_t cell = cidx(D.g, cx, cy, cz);
+                const R w = (R)(st.w[0][ox] * st.w[1][oy] * sel3(st.w[2], oz));
+                R v[3];
+                load_vec4(C.dudt + 4 * cell, v);
+#pragma unroll
+                for (int b = 0; b < 3; ++b) Du[b] += w * v[b];
+            }
+        }
     }
 }
 
@@ -440,6 +484,11 @@ __global__ __launch_bounds__(kBlock) void k_part_am(Desc D, Cells<R> C)
     load_stencil<R>(P, i, st);
     R Du[3] = {(R)0, (R)0, (R)0};
     R U[3] = {(R)0, (R)0, (R)0}, Om[3] = {(R)0, (R)0, (R)0};
+    if (!LIFT) {
+        interp_dudt<R>(D, C, st, Du);
+        am_force<R>(D, i, Du);
+        return;
+    }
 #pragma unroll 1
     for (int oz = 0; oz < 3; ++oz) {
         const int cz = stencil_coord(st.b[2], oz - 1, D.g.n[2], D.g.per[2]);
@@ -1522,42 +1571,78 @@ __global__ __launch_bounds__(kBlock) void k_cellsort(Desc D)
 
 // gather the particle state into bin order (slot s <- list[s]) and evaluate
 // the kernel stencils of the new positions
-__global__ __launch_bounds__(kBlock) void k_permute(Desc D)
+// moves the particle bound for slot s into the permutation targets and
+// evaluates its kernel stencil; returns what the fused added-mass pass needs
+__device__ __forceinline__ void permute_slot(const Desc &D, int64_t s, double x[3], double u[3], double acc[3],
+                                             double &d, Stencil &st)
 {
-    const int64_t s = gidx();
     const Parts &P = D.pt;
-    if (s >= P.np) return;
     const int64_t cap = P.cap;
     const int src = D.b.list[s];
-    double x[3], u[3], w[3];
+    double w[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         x[a] = P.x[a * cap + src];
         u[a] = P.u[a * cap + src];
         w[a] = P.w[a * cap + src];
+        acc[a] = P.a[a * cap + src];
         P.x2[a * cap + s] = x[a];
         P.u2[a * cap + s] = u[a];
         P.w2[a * cap + s] = w[a];
-        P.a2[a * cap + s] = P.a[a * cap + src];
+        P.a2[a * cap + s] = acc[a];
         int b;
         double wt[3];
         axis_weights(x[a], D.g.n[a], D.g.per[a], b, wt);
         P.sb[a * cap + s] = b;
+        st.b[a] = b;
         if (P.swf) {
 #pragma unroll
-            for (int o = 0; o < 3; ++o) P.swf[(3 * a + o) * cap + s] = (float)wt[o];
+            for (int o = 0; o < 3; ++o) {
+                P.swf[(3 * a + o) * cap + s] = (float)wt[o];
+                st.w[a][o] = (double)(float)wt[o];
+            }
         } else {
 #pragma unroll
-            for (int o = 0; o < 3; ++o) P.sw[(3 * a + o) * cap + s] = wt[o];
+            for (int o = 0; o < 3; ++o) {
+                P.sw[(3 * a + o) * cap + s] = wt[o];
+                st.w[a][o] = wt[o];
+            }
         }
     }
-    const double d = P.d[src], rho = P.rho[src];
+    d = P.d[src];
+    const double rho = P.rho[src];
     P.d2[s] = d;
     P.rho2[s] = rho;
     const int pid = P.id[src];
     P.id2[s] = pid;
     P.slot_of[pid] = (int)s;
     if (P.pk2) store_rec(P.pk2, s, x, u, w, d, rho);
+}
+
+__global__ __launch_bounds__(kBlock) void k_permute(Desc D)
+{
+    const int64_t s = gidx();
+    if (s >= D.pt.np) return;
+    double x[3], u[3], a[3], d;
+    Stencil st;
+    permute_slot(D, s, x, u, a, d, st);
+}
+
+// the permutation followed by the next subcycle's added-mass force of the
+// particle (a4 without lift): the stencil, position, velocity and du_p/dt are
+// already in registers. The stored-precision weights and the summation order
+// are those of k_part_am, so the forces are bit-identical.
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_permute_am(Desc D, Cells<R> C)
+{
+    const int64_t s = gidx();
+    if (s >= D.pt.np) return;
+    double x[3], u[3], a[3], d;
+    Stencil st;
+    permute_slot(D, s, x, u, a, d, st);
+    R Du[3] = {(R)0, (R)0, (R)0};
+    interp_dudt<R>(D, C, st, Du);
+    am_store<R>(D, s, Du, d, a, u, x);
 }
 
 // ---------------------------------------------------------------------------
@@ -2003,6 +2088,11 @@ void launch_sort_permute(const Desc &D, hipStream_t s)
     hipLaunchKernelGGL(k_cellsort, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D);
     if (D.pt.np > 0) hipLaunchKernelGGL(k_permute, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
 }
+template <typename R> void launch_sort_permute_am(const Desc &D, const Cells<R> &C, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cellsort, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D);
+    if (D.pt.np > 0) hipLaunchKernelGGL(k_permute_am<R>, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, C);
+}
 void launch_zero_int(int *p, int64_t n, hipStream_t s) { launch_zero<int>(p, n, s); }
 void launch_set_int(int *p, int v, hipStream_t s)
 {
@@ -2017,6 +2107,7 @@ void launch_set_step(long long *stepc, long long v, hipStream_t s)
     template void launch_moments<R>(const Desc &, const Cells<R> &, hipStream_t);                          \
     template void launch_cellfields<R>(const Desc &, const Cells<R> &, hipStream_t);                       \
     template void launch_curl<R>(const Desc &, const Cells<R> &, hipStream_t);                            \
+    template void launch_sort_permute_am<R>(const Desc &, const Cells<R> &, hipStream_t);                 \
     template void launch_part_am<R>(const Desc &, const Cells<R> &, hipStream_t);                          \
     template void launch_gather_am<R>(const Desc &, const Cells<R> &, hipStream_t);                        \
     template void launch_part_drag<R>(const Desc &, const Cells<R> &, int, hipStream_t);                        \
