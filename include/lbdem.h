@@ -143,9 +143,11 @@ const char *lbdem_last_error(lbdem_domain_t h);
 lbdem_status lbdem_params_default(lbdem_params *p);
 
 /* Route device allocations through a caller allocator (e.g. a framework's
- * caching allocator). alloc returns device memory of `bytes` or NULL; free
- * releases it. Pass NULLs to restore hipMalloc/hipFree. Applies to domains
- * created afterwards. */
+ * caching allocator). alloc returns device memory of `bytes`, aligned to 256
+ * bytes as hipMalloc's is, or NULL (E_OOM); a misaligned block is released
+ * and the call that needed it fails with E_INVALID. free releases a block.
+ * Pass NULLs to restore hipMalloc/hipFree. Applies to domains created
+ * afterwards. */
 lbdem_status lbdem_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
                                  void (*free_fn)(void *ptr, void *ctx), void *ctx);
 

@@ -113,6 +113,11 @@ struct lbdem_domain {
         if (al.alloc) {
             p = al.alloc(bytes, al.ctx);
             if (!p) throw Oom{bytes};
+            // vector loads of packed records and counts assume hipMalloc's alignment
+            if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {
+                if (al.free_fn) al.free_fn(p, al.ctx);
+                throw std::runtime_error("the caller allocator returned a block not aligned to 256 bytes");
+            }
         } else {
             hipError_t e = hipMalloc(&p, bytes);
             if (e != hipSuccess) {

@@ -1464,14 +1464,23 @@ __global__ __launch_bounds__(kBlock) void k_scan_block(Desc D)
     __shared__ int wsum[kBlock / 64];
     const int64_t nc = D.g.nc;
     const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + (int64_t)threadIdx.x * kScanItems;
+    static_assert(kScanItems == 8, "two 16-byte vectors per thread");
+    // a thread's 8 counts are 32-byte aligned: two vector loads, scalar
+    // loads only for the last, ragged chunk
+    const bool full = base + kScanItems <= nc;
     int v[kScanItems];
+    if (full) {
+        const int4 a = *reinterpret_cast<const int4 *>(D.b.cnt + base);
+        const int4 b = *reinterpret_cast<const int4 *>(D.b.cnt + base + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int t = 0; t < kScanItems; ++t) v[t] = base + t < nc ? D.b.cnt[base + t] : 0;
+    }
     int tot = 0;
 #pragma unroll
-    for (int t = 0; t < kScanItems; ++t) {
-        const int64_t c = base + t;
-        v[t] = c < nc ? D.b.cnt[c] : 0;
-        tot += v[t];
-    }
+    for (int t = 0; t < kScanItems; ++t) tot += v[t];
     // wavefront-shuffle scan, then the wavefront totals (one barrier)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int incl = tot;
@@ -1489,14 +1498,24 @@ __global__ __launch_bounds__(kBlock) void k_scan_block(Desc D)
         if (w < wv) run += ws;
         btot += ws;
     }
+    int o[kScanItems];
 #pragma unroll
     for (int t = 0; t < kScanItems; ++t) {
-        const int64_t c = base + t;
-        if (c < nc) {
-            D.b.loc[c] = run;
-            D.b.cnt[c] = 0;
-        }
+        o[t] = run;
         run += v[t];
+    }
+    if (full) {
+        *reinterpret_cast<int4 *>(D.b.loc + base) = make_int4(o[0], o[1], o[2], o[3]);
+        *reinterpret_cast<int4 *>(D.b.loc + base + 4) = make_int4(o[4], o[5], o[6], o[7]);
+        *reinterpret_cast<int4 *>(D.b.cnt + base) = make_int4(0, 0, 0, 0);
+        *reinterpret_cast<int4 *>(D.b.cnt + base + 4) = make_int4(0, 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int t = 0; t < kScanItems; ++t)
+            if (base + t < nc) {
+                D.b.loc[base + t] = o[t];
+                D.b.cnt[base + t] = 0;
+            }
     }
     if (threadIdx.x == kBlock - 1) D.b.bsum[blockIdx.x] = btot;
 }
