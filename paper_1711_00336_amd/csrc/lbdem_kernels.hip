@@ -591,9 +591,10 @@ __device__ __forceinline__ void gather_cell(const Desc &D, int i, int j, int k, 
 // ---------------------------------------------------------------------------
 // LDS-tiled gather. A workgroup owns a TX x TY x (TZ*CZ) tile of cells, each
 // thread CZ consecutive cells along z. It counts the particles of the tile's
-// halo bins (the tile widened by one cell, wrapped on periodic axes), stages
-// their stencils and values into LDS (a bin's particles are one contiguous
-// slot range, staged by the thread that owns the bin), and then every cell
+// halo bins (the tile widened by one cell, wrapped on periodic axes), lists
+// their slots in LDS (a bin's particles are one contiguous slot range, listed
+// by the thread that owns the bin), stages their stencils and values into
+// LDS one entry per thread (independent, coalesced loads), and then every cell
 // sums the particles of its own 3x3x3 bins from LDS, in the order
 // (dz, dy, dx, slot) whatever the tile shape. Tiles whose halo holds more
 // than KMAX particles fall back to the per-cell global gather.
@@ -696,6 +697,7 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
     // FP32 form); products are accumulated in FP64
     __shared__ R sw_l[9][KMAX];
     __shared__ R sv_l[NV][KMAX];
+    __shared__ int sslot[KMAX];  // particle slot of each staged entry
 
     const int tid = threadIdx.x;
     const int n0 = D.g.n[0], n1 = D.g.n[1], n2 = D.g.n[2];
@@ -753,17 +755,24 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
         if (w < wv) run += ws;
         K += ws;
     }
-    // offsets of the halo bins, and the staging of their particles (stencil
-    // weights and values) by the thread that owns the bin
+    // offsets of the halo bins and the particle slot of every staged entry
+    // (written by the thread that owns the bin: LDS stores only) ...
     const Parts &P = D.pt;
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
         const int hb = tid * PER + t;
         if (hb < NHB) hoff[hb] = run;
-        for (int q = 0; q < cnt[t]; ++q) {
-            const int kk = run + q;
-            if (kk >= KMAX) break;
-            const int p = src[t] + q;
+        if (K <= KMAX)
+            for (int q = 0; q < cnt[t]; ++q) sslot[run + q] = src[t] + q;
+        run += cnt[t];
+    }
+    if (tid == NT - 1) hoff[NHB] = K;
+    __syncthreads();
+    // ... then the staging of weights and values, one entry per thread, so
+    // that a wavefront's loads are independent (same entries, same order)
+    if (K <= KMAX) {
+        for (int kk = tid; kk < K; kk += NT) {
+            const int p = sslot[kk];
 #pragma unroll
             for (int u = 0; u < 9; ++u) sw_l[u][kk] = stencil_weight<R>(P, u, p);
             double v[NV];
@@ -771,10 +780,8 @@ __global__ __launch_bounds__(TX *TY *TZ) void k_gather_tile(Desc D, Cells<R> C)
 #pragma unroll
             for (int u = 0; u < NV; ++u) sv_l[u][kk] = (R)v[u];
         }
-        run += cnt[t];
+        __syncthreads();
     }
-    if (tid == NT - 1) hoff[NHB] = K;
-    __syncthreads();
 
     const int tx = tid % TX, ty = (tid / TX) % TY, tz = tid / (TX * TY);
     const int i = x0 + tx, j = y0 + ty, kb = z0 + tz * CZ;
