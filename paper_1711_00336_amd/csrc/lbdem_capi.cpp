@@ -343,6 +343,7 @@ void swap_particle_buffers(lbdem_domain_t h)
     std::swap(P.d, P.d2);
     std::swap(P.rho, P.rho2);
     std::swap(P.id, P.id2);
+    std::swap(P.bslot, P.bslot2);
     std::swap(P.pk, P.pk2);
 }
 
@@ -394,7 +395,7 @@ void alloc_particles(lbdem_domain_t h, int64_t cap)
         vec.push_back(&P.Fl_id);
     }
     double **sca[] = {&P.d, &P.rho, &P.d2, &P.rho2};
-    int **ints[] = {&P.id, &P.id2};
+    int **ints[] = {&P.id, &P.id2, &P.bslot, &P.bslot2};
     for (double **v : vec) { h->dfree(*v); *v = nullptr; }
     for (double **v : sca) { h->dfree(*v); *v = nullptr; }
     for (int **v : ints) { h->dfree(*v); *v = nullptr; }

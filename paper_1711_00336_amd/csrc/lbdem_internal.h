@@ -92,9 +92,12 @@ struct Parts {
     double *ustart, *xstart;    // velocity / position at subcycle start
     double *Fam_id, *Fd_id, *Fpr_id, *Fc_id;  // last subcycle's forces by insertion index
     double *Fl, *Fl_id;         // lift (slot order; last subcycle by insertion index), lift only
-    // Verlet lists by insertion index: nlist[id*nbr + t], nnb[id] entries,
-    // built from positions xbuild[3][cap] (by id); slot_of[id] = current slot
+    // Verlet lists labelled by the slot a particle had when the lists were
+    // built (bslot[slot], carried through the reorders): nlist[label*nbr + t]
+    // holds neighbour labels in ascending insertion index, nnb[label] entries,
+    // build positions xbuild[3][cap] by label; slot_of[label] = current slot
     int *nlist, *nnb, *slot_of;
+    int *bslot, *bslot2;        // label of the particle in each slot (+ permutation target)
     int nbr;                    // list capacity per particle (sized from the density and reach)
     double *xbuild;
     int *need;                  // 1: rebuild the lists before the next DEM substep

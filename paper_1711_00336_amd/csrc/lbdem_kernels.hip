@@ -1299,7 +1299,10 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
     const int64_t i = gidx();
     if (i >= P.np) return;
     const int64_t cap = P.cap;
-    const int me = P.id[i];
+    // lists are labelled by the slot at build time (particles keep their
+    // label through the reorders and move little, so labels stay close to
+    // slots and the label-indexed arrays are read almost in order)
+    const int me = (int)i;
     const double xi0 = P.x[i], xi1 = P.x[cap + i], xi2 = P.x[2 * cap + i];
     const double ri = 0.5 * P.d[i];
     const double gap = (D.p.use_lub ? fmax(D.p.h_c, 0.0) : 0.0) + D.p.vskin;
@@ -1329,14 +1332,16 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
                     const double reach = ri + 0.5 * P.d[j] + gap;
                     if (dot3(dx, dx) >= reach * reach) continue;
                     if (m < P.nbr) {
-                        // insertion by ascending insertion index
-                        const int v = P.id[j];
+                        // the neighbour's label (its slot now), kept in
+                        // ascending insertion index, so the pair sums run in
+                        // an order that does not depend on when the list was built
+                        const int key = P.id[j];
                         int t = m - 1;
-                        while (t >= 0 && L[t] > v) {
+                        while (t >= 0 && P.id[L[t]] > key) {
                             L[t + 1] = L[t];
                             --t;
                         }
-                        L[t + 1] = v;
+                        L[t + 1] = j;
                     }
                     ++m;
                 }
@@ -1349,6 +1354,8 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
     P.xbuild[me] = xi0;
     P.xbuild[cap + me] = xi1;
     P.xbuild[2 * cap + me] = xi2;
+    P.bslot[i] = me;
+    P.slot_of[me] = (int)i;
 }
 
 // contact + lubrication force and torque on every particle from its list.
@@ -1367,7 +1374,7 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
     load_particle<T, REC>(P, i, pi);
     T F[3] = {(T)0, (T)0, (T)0}, Tq[3] = {(T)0, (T)0, (T)0};
     const double gap = D.p.use_lub ? fmax(D.p.h_c, 0.0) : 0.0;
-    const int me = P.id[i];
+    const int me = P.bslot[i];
     const int n = P.nnb[me];
     const int *L = P.nlist + (int64_t)me * P.nbr;
     constexpr int kChunk = 2;
@@ -1437,7 +1444,7 @@ __global__ __launch_bounds__(kBlock) void k_integrate(Desc D, int last)
         if (fabs(dx) > D.p.skin) bad |= FLAG_SKIN;
         if (last) P.a[k] = (u - P.ustart[k]) / D.p.dt_int;
         if (last) {
-            double db = xa - P.xbuild[a * cap + P.id[i]];
+            double db = xa - P.xbuild[a * cap + P.bslot[i]];
             if (D.g.per[a]) db -= L * rint(db / L);
             moved = fmax(moved, fabs(db));
         }
@@ -1639,9 +1646,10 @@ __device__ __forceinline__ void permute_slot(const Desc &D, int64_t s, double x[
     const double rho = P.rho[src];
     P.d2[s] = d;
     P.rho2[s] = rho;
-    const int pid = P.id[src];
-    P.id2[s] = pid;
-    P.slot_of[pid] = (int)s;
+    P.id2[s] = P.id[src];
+    const int lab = P.bslot[src];
+    P.bslot2[s] = lab;
+    P.slot_of[lab] = (int)s;
     if (P.pk2) store_rec(P.pk2, s, x, u, w, d, rho);
 }
 
