@@ -216,11 +216,13 @@ lbdem_status lbdem_load_state(lbdem_domain_t h, const void *blob, size_t size);
  * lbdem_kernel_time returns the total device time in ms and the number of
  * launches of one kernel class since timing was switched on. Classes:
  * 0 stream-collide, 1 moments, 2 cell fields (Du/Dt, grad P), 3 added-mass
- * particle pass, 4 drag/pressure particle pass, 5 added-mass spreading,
- * 6 drag spreading and f_acc, 7 volume fraction (+ next added-mass
- * spreading), 8 Verlet list build, 9 DEM contact/lubrication forces,
- * 10 DEM integration, 11 particle binning and reordering, 12 subcycle
- * u_f and its curl (lift only). E_INVALID for a class outside 0..12. */
+ * particle pass (first subcycle; without lift the later subcycles' added
+ * mass runs inside class 11), 4 drag/pressure particle pass, 5 added-mass
+ * spreading, 6 drag spreading and f_acc, 7 volume fraction (+ next
+ * added-mass spreading), 8 Verlet list build, 9 DEM contact/lubrication
+ * forces, 10 DEM integration, 11 particle binning and reordering, 12
+ * subcycle u_f and its curl (lift only). E_INVALID for a class outside
+ * 0..12. */
 lbdem_status lbdem_set_timing(lbdem_domain_t h, int on);
 lbdem_status lbdem_kernel_time(lbdem_domain_t h, int cls, double *ms_total, int64_t *launches);
 
