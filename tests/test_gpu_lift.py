@@ -137,3 +137,29 @@ def test_curl_and_lift_need_lift_on(L):
         with pytest.raises(L.LbdemError) as e:
             dom.lbdem_read_particle_lift()
         assert e.value.status == L.E_STATE
+
+
+@pytest.mark.parametrize("n", [(2, 9, 10), (9, 2, 10)])
+def test_lift_thin_periodic_axis(L, n):
+    """A periodic axis of 2 cells (x or y) with lift and the per-cell
+    relaxation time: the curl's stencil, the kernel stencils and the
+    neighbour bins wrap onto themselves (the gathers take their per-cell
+    form)."""
+    prm = I.Params(n=n, periodic=(1, 1, 0), tau=0.9, gravity=(0, 0, -1e-5), h_c=0.5, n_int=10,
+                   precision="fp64", use_lift=1, use_eilers=1, use_les=1)
+    parts = I.make_particles(6, prm, 6, 0.5, 0.5, 2.0)
+    case = _stirred(I.Case("thin-axis-lift", prm, parts, 6), 4, 1e-3)
+    _say(f"case {case.name} n {n} np {case.particles.n}")
+    o = warm_oracle(case, 2)
+    with L.Domain(case.params) as dom:
+        for s in range(2):
+            load_oracle_state(dom, o.state)
+            dom.step(1)
+            r = o.step(1, aux=True)
+            assert r["status"] == 0
+            errs, bad = compare_states(dom.lbdem_get_state(), o.state, case.params, TOL64)
+            assert not bad, (s, errs)
+        got = dom.lbdem_read_particle_lift()
+    assert np.abs(r["F_l"]).max() > 0
+    assert rel_err(got, r["F_l"]) <= TOL64
+    _say(f"  rel errors {errs}")
