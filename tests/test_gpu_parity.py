@@ -300,3 +300,34 @@ def test_graph_replay_equals_direct_launches(L):
             out.append(dom.lbdem_get_state())
     for k in ("df", "uprev", "x", "u", "w", "a"):
         assert np.array_equal(out[0][k], out[1][k]), k
+
+
+def test_misaligned_caller_allocator_rejected(L):
+    """A caller allocator that returns blocks off the 256-byte alignment is
+    refused with E_INVALID, and every block it handed out is released."""
+    import ctypes as C
+    import torch
+    held = {}
+
+    def alloc(nbytes, ctx):
+        t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device="cuda")
+        p = t.data_ptr() + 16
+        held[p] = t
+        return p
+
+    def free(ptr, ctx):
+        held.pop(ptr, None)
+
+    a, f = L._ALLOC_FN(alloc), L._FREE_FN(free)
+    case = I.case_small_walled(0)
+    try:
+        L._check(None, L.lib().lbdem_set_allocator(C.cast(a, C.c_void_p), C.cast(f, C.c_void_p), None))
+        with pytest.raises(L.LbdemError) as e:
+            L.Domain(case.params)
+        assert e.value.status == L.E_INVALID
+    finally:
+        L.use_torch_allocator(False)
+    torch.cuda.synchronize()
+    assert not held
+    with L.Domain(case.params) as dom:  # hipMalloc again
+        dom.step(1)
