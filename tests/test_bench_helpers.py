@@ -1,0 +1,74 @@
+"""Host logic of the benchmark: the measured-traffic lookup reports a value only
+for counters taken on the current kernel source (and gather variant), and the
+algorithmic byte counts follow their stated per-unit figures."""
+import hashlib
+import importlib.util
+import os
+
+import numpy as np
+import pytest
+
+from paper_1711_00336_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def _summary(path, sha, nbytes, variant=None):
+    lines = ["# test summary", "", "Machine-readable (read by bench.py):", "",
+             f"- kernel_source_sha256: `{sha}`", f"- hbm_bytes_per_launch: {nbytes}"]
+    if variant is not None:
+        lines.append(f"- gather_variant: {variant}")
+    path.write_text("\n".join(lines) + "\n")
+
+
+def test_measured_traffic_only_for_current_source(bench, tmp_path, monkeypatch):
+    src = tmp_path / "kernels.hip"
+    src.write_text("// kernel source v1\n")
+    monkeypatch.setattr(bench, "KERNEL_SRC", str(src))
+    monkeypatch.setattr(bench, "PROFILES", str(tmp_path))
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    _summary(tmp_path / "traffic_gather_eps_dilute.md", sha, 123456789, variant=0)
+    assert bench.measured_traffic("gather_eps", "dilute", 0) == 123456789
+    assert bench.measured_traffic("gather_eps", "dilute", None) == 123456789
+    # counters taken with another launch shape
+    assert bench.measured_traffic("gather_eps", "dilute", 2) is None
+    # no summary for this kernel and workload
+    assert bench.measured_traffic("dem_force", "dilute", 0) is None
+    # the kernel source changed since the counters were taken
+    src.write_text("// kernel source v2\n")
+    assert bench.measured_traffic("gather_eps", "dilute", 0) is None
+
+
+def test_committed_summaries_are_well_formed(bench):
+    """Every committed traffic summary carries the fields bench.py reads."""
+    names = [n for n in os.listdir(bench.PROFILES) if n.startswith("traffic_")]
+    assert names
+    for n in names:
+        text = open(os.path.join(bench.PROFILES, n)).read()
+        assert "- kernel_source_sha256: `" in text, n
+        v = [l for l in text.splitlines() if l.startswith("- hbm_bytes_per_launch:")]
+        assert len(v) == 1 and float(v[0].split(":")[1]) > 0, n
+
+
+def test_kernel_bytes_per_unit_figures(bench):
+    prm = I.Params(n=(16, 8, 4), periodic=(1, 1, 1), precision="fp32dev")
+    parts = I.Particles(np.zeros((10, 3)), np.zeros((10, 3)), np.zeros((10, 3)), np.full(10, 0.5), np.full(10, 2.0))
+    case = I.Case("t", prm, parts, 0)
+    nc, n = 16 * 8 * 4, 10
+    kb = bench.kernel_bytes(case, 4.0)
+    assert kb["stream_collide"] == nc * 42 * 4
+    assert kb["gather_eps"] == nc * 11 * 4 + n * 104
+    assert kb["dem_force"] == n * (140 + 16)
+    assert kb["part_am"] == n * 140 + nc * 3 * 4
+    lift = bench.kernel_bytes(I.Case("t", prm.copy(use_lift=1), parts, 0), 4.0)
+    assert lift["part_am"] == n * 188 + nc * 9 * 4 and lift["curl"] == nc * 6 * 4
+    fp64 = bench.kernel_bytes(I.Case("t", prm.copy(precision="fp64"), parts, 0), 4.0)
+    assert fp64["stream_collide"] == 2 * kb["stream_collide"]
