@@ -116,3 +116,23 @@ def test_momentum_budget_with_per_cell_tau(orc):
     # and the per-cell tau changed the result
     P0 = _P(orc, 0.73, eilers=0, les=0, n=n)
     assert np.abs(orc.lbm_collide_stream(P0, df, e, f) - out).max() > 1e-6 * np.abs(df).max()
+
+
+def test_coupled_momentum_budget_with_all_models(orc):
+    """Full coupled steps with lift, the Eilers viscosity and the LES on
+    together: total momentum still changes only by the external impulses
+    (body force, pressure force, submerged weight)."""
+    c = I.case_settling(9, 12, 0.2, 0.8, 2.5, precision="fp64")
+    c.particles.u[:] = np.random.default_rng(6).normal(size=c.particles.u.shape) * 1e-3
+    o = orc.Oracle(c.params.copy(use_lift=1, use_eilers=1, use_les=1), c.particles)
+    m = c.particles.rho_p * np.pi * c.particles.d ** 3 / 6
+    for _ in range(5):
+        d0 = o.diagnostics()
+        r = o.step(1, aux=True)
+        assert r["status"] == 0
+        d1 = o.diagnostics()
+        dP = (d1["mom_fluid"] + d1["mom_part"]) - (d0["mom_fluid"] + d0["mom_part"])
+        ext = r["impulse_fb"] + r["impulse_pr"] + r["impulse_gb"]
+        scale = np.abs(m[:, None] * o.state.u).sum() + 1e-3 * np.abs(r["impulse_gb"]).sum()
+        assert np.abs(dP - ext).max() < 1e-11 * scale, (dP, ext)
+        assert abs(d1["mass_dev"] - d0["mass_dev"]) < 1e-13
