@@ -24,6 +24,12 @@
  *     restitution, rolling, antisymmetry).
  *   - Lattice curl and lift: pinned (closed-form curl of sinusoidal and
  *     wall-bounded linear fields; Saffman's lift in a linear shear).
+ *   - Lattice gradient in grad P and in the convective part of Du_f/Dt:
+ *     pinned (closed forms on sinusoidal and product fields, the wall ghost
+ *     rules on linear fields).
+ *   - Tenneti drag away from eps_p = 0: pinned (its dilute, close-packed and
+ *     inertial limits, hand-evaluated values, the quadratic large-slip form
+ *     that fixes the Reynolds number).
  *   - Per-cell relaxation time (Eilers, Smagorinsky): pinned (Einstein's
  *     dilute limit; Smagorinsky's nu_t = (C_s dx)^2 |S| on Chapman-Enskog
  *     non-equilibrium states; Poiseuille flow with the Eilers viscosity).
@@ -982,7 +988,7 @@ int orc_step(const orc_params *pin, orc_state *s, orc_aux *aux)
         for (int64_t i = 0; i < np; ++i) particle_stencil(p, s->x + 3 * i, &st[i]);
 
         /* (b) u_f = (j + f_ext/2) / (rho eps_f) at the subcycle start and its
-         *     lattice curl (Alg. 1 "Evaluate and store u_f, grad P, curl u_f") */
+         *     lattice curl (Alg. 1, first step of the subcycle loop) */
         if (p->use_lift) {
             for (int64_t c = 0; c < nc; ++c)
                 for (int a = 0; a < 3; ++a)

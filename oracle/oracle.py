@@ -6,6 +6,7 @@ only consumes the seeded inputs of paper_1711_00336_amd.inputs.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -72,42 +73,75 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        L = C.CDLL(_LIB)
-        dp = C.POINTER(C.c_double)
-        L.orc_roma.restype = C.c_double
-        L.orc_roma.argtypes = [C.c_double]
-        L.orc_axis_stencil.restype = C.c_int
-        L.orc_axis_stencil.argtypes = [C.c_double, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
-        L.orc_drag_factor.restype = C.c_double
-        L.orc_drag_factor.argtypes = [C.c_double, C.c_double]
-        L.orc_drag.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p]
-        L.orc_lift.argtypes = [C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_curl_field.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p]
-        L.orc_tau_e.restype = C.c_double
-        L.orc_tau_e.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_void_p, C.c_void_p]
-        L.orc_feq_dev.argtypes = [C.c_double, C.c_void_p, C.c_double, C.c_void_p]
-        L.orc_guo.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_double, C.c_void_p]
-        L.orc_moments.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_collision_params.argtypes = [C.c_double] * 3 + [C.c_void_p, C.c_void_p]
-        L.orc_lub_coeffs.argtypes = [C.c_double] * 3 + [C.c_void_p, C.c_void_p]
-        L.orc_lbm_collide_stream.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_eps_field.argtypes = [C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
-        L.orc_interp_scalar.restype = C.c_double
-        L.orc_interp_scalar.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p]
-        L.orc_spread_scalar.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_double]
-        L.orc_pair_force.argtypes = ([C.POINTER(Params)] + [C.c_void_p] * 3 + [C.c_double, C.c_double]
-                                     + [C.c_void_p] * 3 + [C.c_double, C.c_double] + [C.c_double, C.c_void_p, C.c_void_p])
-        L.orc_wall_force.argtypes = ([C.POINTER(Params)] + [C.c_void_p] * 3 + [C.c_double, C.c_double]
-                                     + [C.c_double, C.c_void_p, C.c_void_p])
-        L.orc_dem_forces.argtypes = ([C.POINTER(Params), C.c_int64] + [C.c_void_p] * 5
-                                     + [C.c_double, C.c_void_p, C.c_void_p])
-        L.orc_step.restype = C.c_int
-        L.orc_step.argtypes = [C.POINTER(Params), C.POINTER(State), C.POINTER(Aux)]
-        L.orc_diagnostics.argtypes = [C.POINTER(Params), C.POINTER(State), C.POINTER(Diag)]
-        L.orc_num_threads.restype = C.c_int
-        L.orc_set_celllist_threshold.argtypes = [C.c_int64]
-        _lib = L
+        _lib = _load(_LIB)
     return _lib
+
+
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile a modified copy of the oracle source (the tests plant known
+    mistakes in it to show that the pins catch them)."""
+    src_path = out_path + ".c"
+    with open(src_path, "w") as fh:
+        fh.write(src_text)
+    subprocess.check_call(["gcc", "-std=gnu11", "-O1", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+                           "-w", "-o", out_path, src_path, "-lm"])
+    return out_path
+
+
+def source() -> str:
+    with open(_SRC) as fh:
+        return fh.read()
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Route every call of this module through another build of the oracle
+    (a variant from build_variant) inside the block."""
+    global _lib
+    saved = _lib
+    _lib = _load(path)
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def _load(path):
+    L = C.CDLL(path)
+    dp = C.POINTER(C.c_double)
+    L.orc_roma.restype = C.c_double
+    L.orc_roma.argtypes = [C.c_double]
+    L.orc_axis_stencil.restype = C.c_int
+    L.orc_axis_stencil.argtypes = [C.c_double, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+    L.orc_drag_factor.restype = C.c_double
+    L.orc_drag_factor.argtypes = [C.c_double, C.c_double]
+    L.orc_drag.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p]
+    L.orc_lift.argtypes = [C.c_double, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_curl_field.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p]
+    L.orc_tau_e.restype = C.c_double
+    L.orc_tau_e.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_void_p, C.c_void_p]
+    L.orc_feq_dev.argtypes = [C.c_double, C.c_void_p, C.c_double, C.c_void_p]
+    L.orc_guo.argtypes = [C.c_void_p, C.c_double, C.c_void_p, C.c_double, C.c_void_p]
+    L.orc_moments.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_collision_params.argtypes = [C.c_double] * 3 + [C.c_void_p, C.c_void_p]
+    L.orc_lub_coeffs.argtypes = [C.c_double] * 3 + [C.c_void_p, C.c_void_p]
+    L.orc_lbm_collide_stream.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_eps_field.argtypes = [C.POINTER(Params), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+    L.orc_interp_scalar.restype = C.c_double
+    L.orc_interp_scalar.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p]
+    L.orc_spread_scalar.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_double]
+    L.orc_pair_force.argtypes = ([C.POINTER(Params)] + [C.c_void_p] * 3 + [C.c_double, C.c_double]
+                                 + [C.c_void_p] * 3 + [C.c_double, C.c_double] + [C.c_double, C.c_void_p, C.c_void_p])
+    L.orc_wall_force.argtypes = ([C.POINTER(Params)] + [C.c_void_p] * 3 + [C.c_double, C.c_double]
+                                 + [C.c_double, C.c_void_p, C.c_void_p])
+    L.orc_dem_forces.argtypes = ([C.POINTER(Params), C.c_int64] + [C.c_void_p] * 5
+                                 + [C.c_double, C.c_void_p, C.c_void_p])
+    L.orc_step.restype = C.c_int
+    L.orc_step.argtypes = [C.POINTER(Params), C.POINTER(State), C.POINTER(Aux)]
+    L.orc_diagnostics.argtypes = [C.POINTER(Params), C.POINTER(State), C.POINTER(Diag)]
+    L.orc_num_threads.restype = C.c_int
+    L.orc_set_celllist_threshold.argtypes = [C.c_int64]
+    return L
 
 
 def _p(a):

@@ -265,7 +265,8 @@ __device__ __forceinline__ int ghost(const Nbh &h, int q, double &sign)
 }
 
 // ---------------------------------------------------------------------------
-// a2/a3: per-step cell fields (Alg. 1, "Evaluate and store Du_f/Dt"):
+// a2/a3: per-step cell fields (Alg. 1, the step before the subcycle loop,
+// which keeps the material derivative fixed for the whole LBM step):
 //   u_f^n = (j + eps_f f_b / 2) / (rho eps_f)      (Eq. MacVel, u_f = u_bar/eps_f)
 //   Du_f/Dt = (u_f^n - u_prev) + (u_f^n . grad_L) u_f^n (0 time part at step 0)
 //   grad P = (1/c_s^2) sum_q w_q c_q P(x+c_q) = sum_q w_q c_q (rho-1)(x+c_q)
@@ -322,9 +323,9 @@ __global__ __launch_bounds__(kBlock) void k_cellfields(Desc D, Cells<R> C)
 }
 
 // ---------------------------------------------------------------------------
-// Lift only, at every subcycle start (Alg. 1, "Evaluate and store u_f,
-// grad P, curl u_f"; grad P depends on rho alone and comes from the per-step
-// pass): the lattice curl of Sec. 3.2.3,
+// Lift only, at every subcycle start (Alg. 1, the first step inside the
+// subcycle loop, which also needs u_f; grad P depends on rho alone and comes
+// from the per-step pass): the lattice curl of Sec. 3.2.3,
 //   curl u_f(x) = (1/c_s^2) sum_q w_q c_q x u_f(x + c_q),
 // of the subcycle-start u_f = (j + eps_f f_b / 2) / (rho eps_f) that the
 // moments pass (first subcycle) or the volume-fraction gather (later ones)
@@ -851,7 +852,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_cells(Desc D, Cells<R> C)
 // ---------------------------------------------------------------------------
 // a6: pressure-gradient force, drag, gravity + buoyancy (Table 1, Sec. 3.1.2)
 // with u_f re-evaluated from f_ext = eps_f f_b + f_am (Sec. 3.2.3 stability
-// measures; Alg. 1 "Reevaluate u_f").
+// measures; Alg. 1, the u_f update between the two particle loops).
 // ---------------------------------------------------------------------------
 template <typename T> __device__ __forceinline__ T drag_factor(T Re, T ep)
 {
