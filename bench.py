@@ -67,8 +67,18 @@ def _pool_map(fn, items, what):
     return out
 
 
-def workload(name, seed):
+def workload(name, seed, cache=None):
+    """The named workload; cache: an .npz path where a generated particle
+    set is kept for later runs in the same session (the dense packing takes
+    a minute or two on the host)."""
     from paper_1711_00336_amd import inputs as I
+    if cache and name == "dense" and os.path.exists(cache):
+        z = np.load(cache, allow_pickle=False)
+        if int(z["seed"]) != seed:
+            raise SystemExit(f"{cache} holds the packing of seed {int(z['seed'])}, not {seed}")
+        p = I.dense_walled_params((256, 256, 512), "fp32dev")
+        parts = I.Particles(z["x"], np.zeros_like(z["x"]), np.zeros_like(z["x"]), z["d"], z["rho_p"])
+        return I.Case(f"dense-256x256x512-eps0.4", p, parts, seed)
     if name == "dilute":
         return I.case_dilute_periodic(seed, n=128, eps_p=0.05, d=0.8, precision="fp32dev")
     if name == "dilute64":
@@ -77,7 +87,12 @@ def workload(name, seed):
         return I.case_small_walled(seed)
     if name == "dense":
         say = lambda msg: print(f"[bench] packing: {msg}", file=sys.stderr, flush=True)
-        return I.case_dense_walled(seed, n=(256, 256, 512), eps_p=0.4, precision="fp32dev", progress=say)
+        t0 = time.perf_counter()
+        c = I.case_dense_walled(seed, n=(256, 256, 512), eps_p=0.4, precision="fp32dev", progress=say)
+        say(f"{c.particles.n} spheres in {time.perf_counter() - t0:.0f} s")
+        if cache:
+            np.savez(cache, x=c.particles.x, d=c.particles.d, rho_p=c.particles.rho_p, seed=seed)
+        return c
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -101,43 +116,90 @@ def kernel_bytes(case, nlist):
     """Algorithmic HBM bytes per launch of each timed kernel class: what the
     operation must read and write once (re-reads of neighbour cells or
     particles, which a cache can serve, are not counted). rs is the cell
-    storage size (4 B FP32-deviation, 8 B FP64); particle state is FP64.
+    storage size (4 B FP32-deviation, 8 B FP64); ws the stored kernel-weight
+    size (4 B / 8 B); particle state is FP64.
 
       stream_collide  per cell 19 PDF reads + 19 writes + eps_p + f_acc(3)  42 rs
       moments         per cell 19 PDFs + eps_p read, rho, j, u_f written    27 rs
       cellfields      per cell u_f, rho, u_prev read; Du/Dt, grad P,
                       u_prev, f_acc written                                 19 rs
       part_am         per particle stencil (9 weights, 3 ints), a, d, rho
-                      read, F_am written; per cell Du/Dt read        140 B + 3 rs
+                      read, F_am written; per cell Du/Dt read    76 B + 9 ws + 3 rs
                       (with lift also u read, F_l written; per cell u_f
-                      and curl read                                  188 B + 9 rs)
+                      and curl read                             124 B + 9 ws + 9 rs)
       part_drag       per particle stencil, u, d, rho, F_am, id read,
                       F_d, F_const written; per cell u_f, grad P, eps_p
-                      read                                           200 B + 7 rs
+                      read                                      128 B + 9 ws + 7 rs
       gather_am       per cell eps_p, rho, j read, f_am, u_f written;
-                      per particle 9 weights + F_am (+ F_l)   11 rs + 96 B (120 B)
+                      per particle 9 weights + F_am (+ F_l)   11 rs + 9 ws + 24 B (48 B)
       gather_fd       per cell eps_p, f_am, f_acc read, f_acc written;
-                      per particle 9 weights + F_d                    10 rs + 96 B
+                      per particle 9 weights + F_d            10 rs + 9 ws + 24 B
       gather_eps      per cell rho, j read, eps_p, f_am, u_f written;
-                      per particle 9 weights + d + F_am              11 rs + 104 B
+                      per particle 9 weights + d + F_am       11 rs + 9 ws + 32 B
+      nlist           per particle position, diameter, build flag read; a
+                      rebuild writes the list (counted as 0: most launches
+                      only read the flag)                                 0
       dem_force       per particle x, u, omega, d, rho, id, list length,
                       L list entries read, F, T written          140 B + 4 L B
       integrate       per particle x, u, omega, F_const, F, T, d, rho,
                       x_start read; x, u, omega written                 256 B
+      bins            binning and reordering: per particle position read
+                      and bin-list entry (36 B), the bin sort (12 B), the
+                      permutation of x, u, omega, a, d, rho, id, label
+                      (2 x 120 B), new stencil (12 B + 9 ws) and, in the
+                      FP32 form, the 64-byte DEM record; per cell count,
+                      scan and offsets (20 B)     (300 + 9 ws [+ 64]) B + 20 B
       curl (lift)     per cell u_f read, curl written (the subcycle's u_f is
                       evaluated by the moments pass and the volume-fraction
                       gather)                                            6 rs
     """
-    rs = 4 if case.params.precision == "fp32dev" else 8
+    fp32 = case.params.precision == "fp32dev"
+    rs = 4 if fp32 else 8
+    ws = 4 if fp32 else 8
     nc = int(np.prod(case.params.n))
     n = int(case.particles.n)
     lift = bool(getattr(case.params, "use_lift", 0))
     return {"stream_collide": nc * 42 * rs, "moments": nc * 27 * rs, "cellfields": nc * 19 * rs,
-            "part_am": n * 188 + nc * 9 * rs if lift else n * 140 + nc * 3 * rs,
-            "part_drag": n * 200 + nc * 7 * rs,
-            "gather_am": nc * 11 * rs + n * (120 if lift else 96), "gather_fd": nc * 10 * rs + n * 96,
-            "gather_eps": nc * 11 * rs + n * 104,
-            "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * 256, "curl": nc * 6 * rs}
+            "part_am": n * (124 + 9 * ws) + nc * 9 * rs if lift else n * (76 + 9 * ws) + nc * 3 * rs,
+            "part_drag": n * (128 + 9 * ws) + nc * 7 * rs,
+            "gather_am": nc * 11 * rs + n * (9 * ws + (48 if lift else 24)),
+            "gather_fd": nc * 10 * rs + n * (9 * ws + 24),
+            "gather_eps": nc * 11 * rs + n * (9 * ws + 32), "nlist": 0,
+            "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * 256,
+            "bins": n * (300 + 9 * ws + (64 if fp32 else 0)) + nc * 20, "curl": nc * 6 * rs}
+
+
+# DEM pair arithmetic (a8): about 150 FP64 flops per pair evaluation within
+# the interaction reach (2 square roots, a logarithm and 2-3 divisions among
+# them); each unordered pair is evaluated from both of its particles.
+DEM_FLOPS_PER_PAIR = 150
+FP64_VALU_TFLOPS = 78.6  # MI355X dense FP64 vector peak
+
+
+def roofline_entry(cls, times, kb, workload_name, variant, npairs):
+    """Roofline of one kernel class from its measured average launch time:
+    the DEM force pass against the FP64 vector peak (flops of the pairs
+    within reach), every other class against HBM (algorithmic bytes)."""
+    kt = times[cls]
+    t = kt["avg_launch_ms"] * 1e-3
+    if t <= 0:
+        return None
+    total = sum(v["ms_per_step"] for v in times.values())
+    share = round(kt["ms_per_step"] / total, 4) if total > 0 else 0.0
+    traffic = measured_traffic(cls, workload_name, variant)
+    if cls == "dem_force":
+        flops = DEM_FLOPS_PER_PAIR * npairs
+        ach = flops / t / 1e12
+        return {"bound": "alu", "kernel": cls, "achieved": round(ach, 3), "peak": FP64_VALU_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP64_VALU_TFLOPS, 4), "traffic": traffic,
+                "flops_per_launch": int(flops), "pair_evaluations_per_launch": int(npairs),
+                "flops_per_pair": DEM_FLOPS_PER_PAIR, "hbm_bytes_algorithmic": kb[cls],
+                "hbm_achieved_gbs": round(kb[cls] / t / 1e9, 1),
+                "avg_launch_ms": round(kt["avg_launch_ms"], 5), "share_of_step": share}
+    ach = kb[cls] / t / 1e9
+    return {"bound": "hbm", "kernel": cls, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "bytes_per_launch": kb[cls],
+            "avg_launch_ms": round(kt["avg_launch_ms"], 5), "share_of_step": share}
 
 
 PROFILES = os.path.join(ROOT, "profiles")
@@ -411,13 +473,67 @@ def bench_serve(args):
     return lines
 
 
+def run_step_workload(lbdem, torch, case, wl_name, K, W, ksteps, stream, args):
+    """Time K coupled steps (graph replay, inputs resident) after W warm-up
+    steps, then every kernel class over ksteps more steps launched one by
+    one with HIP events; returns the measurements and the rooflines."""
+    print(f"[bench] workload {case.name}: cells {np.prod(case.params.n)}, particles {case.particles.n}",
+          file=sys.stderr, flush=True)
+    dom = lbdem.Domain(case.params, stream=stream.cuda_stream)
+    try:
+        dom.add(case.particles)
+        print(f"[bench] {case.particles.n} particles resident", file=sys.stderr, flush=True)
+        nc = dom.nc
+        variant = dom.lbdem_autotune()
+        print(f"[bench] autotuned gather variant {variant}", file=sys.stderr, flush=True)
+        dom.lbdem_step(W)
+        dom.lbdem_sync()
+        torch.cuda.synchronize()
+        print(f"[bench] warmup {W} steps done", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        dom.lbdem_step(K)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        dom.lbdem_sync()
+        print(f"[bench] timed {K} steps in {dt:.3f} s", file=sys.stderr, flush=True)
+        dom.lbdem_set_timing(True)
+        for k in range(ksteps):
+            dom.lbdem_step(1)
+            dom.lbdem_sync()
+        print(f"[bench] per-kernel timing over {ksteps} steps done", file=sys.stderr, flush=True)
+        times = {}
+        for name in lbdem.KCLASS:
+            ms, n = dom.lbdem_kernel_time(name)
+            times[name] = {"ms_per_step": ms / ksteps, "launches_per_step": n / ksteps,
+                           "avg_launch_ms": (ms / n if n else 0.0)}
+        dom.lbdem_set_timing(False)
+        diag = dom.lbdem_diagnostics()
+    finally:
+        dom.close()
+    nlist = mean_list_length(case)
+    nreach = mean_list_length(case, vskin=0.0)
+    print(f"[bench] mean Verlet-list length {nlist:.2f}, neighbours within reach {nreach:.2f}",
+          file=sys.stderr, flush=True)
+    kb = kernel_bytes(case, nlist)
+    npairs = nreach * case.particles.n
+    roofs = {k: roofline_entry(k, times, kb, wl_name, variant, npairs) for k in times
+             if times[k]["launches_per_step"] > 0}
+    roofs = {k: v for k, v in roofs.items() if v is not None}
+    dom_cls = max(roofs, key=lambda k: times[k]["ms_per_step"])
+    return dict(nc=nc, dt=dt, variant=variant, times=times, roofs=roofs, dominant=dom_cls, diag=diag,
+                nlist=nlist, nreach=nreach)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="dilute")
+    ap.add_argument("--workload", default="dense", help="dense (headline) | dilute | dilute64 | small")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--pack-cache", default=None,
+                    help="npz file that keeps the dense packing between runs of one session")
+    ap.add_argument("--no-dilute", action="store_true", help="skip the 128^3 dilute run beside the dense one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--mode", choices=("step", "batch", "serve", "k10"), default="step")
@@ -429,7 +545,6 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=100)
     ap.add_argument("--edge-hi", type=int, default=160)
     ap.add_argument("--steps-hi", type=int, default=5000)
-    ap.add_argument("--no-k10", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0)
     ap.add_argument("--lift", action="store_true", help="shear-induced lift on (step mode)")
     ap.add_argument("--visc", action="store_true",
@@ -437,9 +552,9 @@ def main():
     args = ap.parse_args()
     dense = args.mode == "step" and args.workload == "dense"
     if args.steps is None:
-        args.steps = 10 if dense else {"step": 200, "batch": 20, "serve": 0, "k10": 0}[args.mode]
+        args.steps = 20 if dense else {"step": 200, "batch": 20, "serve": 0, "k10": 0}[args.mode]
     if args.warmup is None:
-        args.warmup = 3 if dense else {"step": 20, "batch": 3, "serve": 0, "k10": 0}[args.mode]
+        args.warmup = 5 if dense else {"step": 20, "batch": 3, "serve": 0, "k10": 0}[args.mode]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this library runs on one GPU only; --gpus must be 1 "
               "(the spatial decomposition across GPUs is designed, not implemented)", file=sys.stderr)
@@ -459,75 +574,33 @@ def main():
     import torch
     from paper_1711_00336_amd import lbdem
 
-    case = workload(args.workload, args.seed)
+    case = workload(args.workload, args.seed, args.pack_cache)
     if args.lift:
         case.params = case.params.copy(use_lift=1)
         case.name += "+lift"
     if args.visc:
         case.params = case.params.copy(use_eilers=1, use_les=1)
         case.name += "+eilers+les"
-    print(f"[bench] workload {case.name}: cells {np.prod(case.params.n)}, particles {case.particles.n}",
-          file=sys.stderr, flush=True)
     torch.cuda.init()
     stream = torch.cuda.current_stream()
-    dom = lbdem.Domain(case.params, stream=stream.cuda_stream)
-    dom.add(case.particles)
-    nc = dom.nc
-    variant = dom.lbdem_autotune()
-    print(f"[bench] autotuned gather variant {variant}", file=sys.stderr, flush=True)
+    ksteps = 2 if dense else max(5, min(args.steps, 20))
+    r = run_step_workload(lbdem, torch, case, args.workload, args.steps, args.warmup, ksteps, stream, args)
+    times, roofs = r["times"], r["roofs"]
 
-    dom.lbdem_step(args.warmup)
-    dom.lbdem_sync()
-    torch.cuda.synchronize()
-    print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+    side = None
+    if dense and not args.no_dilute:
+        # the 128^3 dilute settling workload beside the headline (resident
+        # inputs, graph replay; its PDFs partly fit in the last-level cache)
+        c2 = workload("dilute", args.seed)
+        r2 = run_step_workload(lbdem, torch, c2, "dilute", 200, 20, 10, stream, args)
+        side = {"workload": c2.name, "cells": int(r2["nc"]), "particles": int(c2.particles.n),
+                "value": round(r2["nc"] * 200 / r2["dt"] / 1e6, 2), "unit": "MLUPS",
+                "ms_per_step": round(r2["dt"] / 200 * 1e3, 4), "steps": 200, "warmup": 20,
+                "roofline": r2["roofs"][r2["dominant"]],
+                "roofline_stream_collide": r2["roofs"].get("stream_collide"),
+                "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in r2["times"].items()},
+                "u_ps": r2["diag"]["u_ps"]}
 
-    t0 = time.perf_counter()
-    dom.lbdem_step(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    dom.lbdem_sync()
-    print(f"[bench] timed {args.steps} steps in {dt:.3f} s", file=sys.stderr, flush=True)
-
-    # per-kernel-class device time (HIP events on the library's stream)
-    ksteps = 3 if dense else max(5, min(args.steps, 20))
-    dom.lbdem_set_timing(True)
-    for k in range(ksteps):
-        dom.lbdem_step(1)
-        dom.lbdem_sync()
-        if dense or k == ksteps - 1:
-            print(f"[bench] per-kernel timing: step {k + 1}/{ksteps}", file=sys.stderr, flush=True)
-    times = {}
-    for name in lbdem.KCLASS:
-        ms, n = dom.lbdem_kernel_time(name)
-        times[name] = {"ms_per_step": ms / ksteps, "launches_per_step": n / ksteps,
-                       "avg_launch_ms": (ms / n if n else 0.0)}
-    dom.lbdem_set_timing(False)
-    diag = dom.lbdem_diagnostics()
-    dom.close()
-
-    nlist = mean_list_length(case)
-    print(f"[bench] mean Verlet-list length {nlist:.2f}", file=sys.stderr, flush=True)
-    kb = kernel_bytes(case, nlist)
-    dom_cls = max((k for k in kb if times[k]["launches_per_step"] > 0), key=lambda k: times[k]["ms_per_step"])
-    kt = times[dom_cls]
-    achieved = kb[dom_cls] / (kt["avg_launch_ms"] * 1e-3) / 1e9 if kt["avg_launch_ms"] > 0 else 0.0
-    roofline = {"bound": "hbm", "kernel": dom_cls, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom_cls, args.workload, variant), "bytes_per_launch": kb[dom_cls],
-                "avg_launch_ms": round(kt["avg_launch_ms"], 5), "share_of_step": round(kt["ms_per_step"] / sum(
-                    v["ms_per_step"] for v in times.values()), 4)}
-    if dom_cls == "dem_force":
-        roofline["mean_list_length"] = round(nlist, 2)
-    roof_curl = None
-    if args.lift and times["curl"]["avg_launch_ms"] > 0:
-        a = kb["curl"] / (times["curl"]["avg_launch_ms"] * 1e-3) / 1e9
-        roof_curl = {"bound": "hbm", "kernel": "curl", "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(a / HBM_PEAK_GBS, 4), "traffic": measured_traffic("curl", args.workload, variant),
-                     "bytes_per_launch": kb["curl"], "avg_launch_ms": round(times["curl"]["avg_launch_ms"], 5)}
-    roof_k10 = None
-    if not args.no_k10:
-        print("[bench] stream-collide alone on the 256x256x512 grid", file=sys.stderr, flush=True)
-        roof_k10 = k10_roofline(lbdem, stream, visc=args.visc)
     if args.calib_copy_mib > 0:
         # a plain device copy of known size, for scaling the HBM byte counters
         nb = args.calib_copy_mib << 20
@@ -544,7 +617,7 @@ def main():
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(case, args.cpu_budget)
 
-    ms_per_step = dt / args.steps * 1e3
+    nc, dt = r["nc"], r["dt"]
     out = {
         "metric": METRIC,
         "value": round(nc * args.steps / dt / 1e6, 2),
@@ -552,7 +625,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -561,14 +634,17 @@ def main():
         "config": {"workload": case.name, "cells": int(nc), "particles": int(case.particles.n),
                    "n_int": case.params.n_int, "n_dem": case.params.n_dem,
                    "pdf_storage": "f32 deviation" if case.params.precision == "fp32dev" else "f64 deviation",
-                   "particle_integration": "f64", "tau": case.params.tau, "gather_variant": variant,
-                   "lift": bool(args.lift), "eilers_les": bool(args.visc)},
-        "roofline": roofline,
-        "roofline_stream_collide": roof_k10,
-        **({"roofline_curl": roof_curl} if args.lift else {}),
+                   "particle_integration": "f64", "tau": case.params.tau, "gather_variant": r["variant"],
+                   "lift": bool(args.lift), "eilers_les": bool(args.visc),
+                   "mean_list_length": round(r["nlist"], 2), "neighbours_within_reach": round(r["nreach"], 2)},
+        "roofline": roofs[r["dominant"]],
+        "roofline_stream_collide": roofs.get("stream_collide"),
+        "rooflines": {k: {kk: v[kk] for kk in ("bound", "achieved", "unit", "frac", "share_of_step")}
+                      for k, v in roofs.items()},
+        **({"dilute_128cubed": side} if side else {}),
         "cpu_baseline": cpu,
         "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in times.items()},
-        "u_ps": diag["u_ps"],
+        "u_ps": r["diag"]["u_ps"],
     }
     print(json.dumps(out), flush=True)
 

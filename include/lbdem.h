@@ -36,9 +36,11 @@ typedef enum {
     LBDEM_OK = 0,
     LBDEM_E_INVALID = 1,   /* bad argument, out-of-domain particle, size mismatch */
     LBDEM_E_OOM = 2,       /* device allocation failed */
-    LBDEM_E_UNSTABLE = 3,  /* non-finite state, eps_f <= 0, particle through a wall,
-                              or a particle moved further than the search skin in
-                              one interaction subcycle */
+    LBDEM_E_UNSTABLE = 3,  /* explicit coupling estimated unstable (add_particles),
+                              non-finite particle or fluid state, |u_bar| > 0.1,
+                              eps_f <= 0, particle through a wall, or a particle
+                              moved further than the search skin in one
+                              interaction subcycle */
     LBDEM_E_DEVICE = 4,    /* HIP runtime error */
     LBDEM_E_BUSY = 5,      /* serving: result not ready / no capacity */
     LBDEM_E_STATE = 6      /* call not valid in the handle's current state */
@@ -151,9 +153,26 @@ lbdem_status lbdem_params_default(lbdem_params *p);
 lbdem_status lbdem_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
                                  void (*free_fn)(void *ptr, void *ctx), void *ctx);
 
+/* Stability estimate of the explicit fluid-particle coupling (Alg. 1: the
+ * fluid forces are frozen over an interaction subcycle of length
+ * dt_int = 1/n_int, and the added mass of Table 1 uses the previous
+ * subcycle's du_p/dt). Host-only: needs no device. For spheres of diameters
+ * d[n] and densities rho_p[n] in the domain p, the slip relaxes with
+ * tau_p = rho_p d^2 / (18 mu f(eps_ref)) (Table 1 drag at Re -> 0, mu from
+ * tau by Eq. visc_tau, eps_ref = max(V_max/8, mean solid fraction)); the
+ * subcycle map of the slip is stable while dt_int < (2 - 2a) tau_p with
+ * a = c_am rho_f / rho_p (a = 0 without added mass). *dt_int_max receives
+ * the smallest (2 - 2a) tau_p over the particles (HUGE_VAL for n = 0).
+ * Returns OK if 1/p->n_int is below it, E_UNSTABLE if not, E_INVALID for a
+ * bad argument. An estimate: the in-step checks remain the authority.
+ * lbdem_add_particles applies it to the domain's whole particle set. */
+lbdem_status lbdem_stability_limit(const lbdem_params *p, int64_t n, const double *d, const double *rho_p,
+                                   double *dt_int_max);
+
 /* Create a domain at rest (all f_q = w_q, no particles) on the current HIP
  * device. hip_stream is a hipStream_t (NULL: the library creates one).
- * E_INVALID if tau <= 1/2, a size < 1, n_int or n_dem < 1. */
+ * E_INVALID if tau <= 1/2, a size < 1, n_int or n_dem < 1. The coupling
+ * stability estimate needs the particles and runs in lbdem_add_particles. */
 lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_t *out);
 
 /* Free everything; NULL is a no-op. */
@@ -162,8 +181,12 @@ lbdem_status lbdem_destroy(lbdem_domain_t h);
 /* Append n spheres (Sec. 3.1): host arrays x,u,omega [n][3], d,rho_p [n].
  * Copied synchronously; the fluid volume fraction (Eq. fluid_volume_fraction)
  * and an automatic f_b are recomputed. E_INVALID if a centre lies outside
- * the domain (on [0, n) of a periodic axis, strictly inside (0, n) between
- * walls), a value is not finite, d <= 0 or rho_p <= 0. */
+ * the domain (on [0, n) of a periodic axis; between walls a sphere may
+ * overlap a wall by less than d/2, i.e. its centre lies strictly inside
+ * (0, n): a centre on or beyond the wall plane is rejected, as the step's
+ * wall check would flag it), a value is not finite, d <= 0 or rho_p <= 0.
+ * E_UNSTABLE, adding nothing, if lbdem_stability_limit rejects the
+ * domain's particles after the addition (raise n_int). */
 lbdem_status lbdem_add_particles(lbdem_domain_t h, int64_t n, const double *x, const double *u,
                                  const double *omega, const double *d, const double *rho_p);
 
@@ -171,7 +194,12 @@ lbdem_status lbdem_add_particles(lbdem_domain_t h, int64_t n, const double *x, c
  * Asynchronous: errors detected on the device surface at lbdem_sync. */
 lbdem_status lbdem_step(lbdem_domain_t h, int64_t nsteps);
 
-/* Wait for the stream; returns E_UNSTABLE if any step flagged instability. */
+/* Wait for the stream; returns E_UNSTABLE if any step flagged instability:
+ * a non-finite particle state, a particle through a wall or beyond the
+ * search skin within a subcycle, eps_f <= 0, more list neighbours than the
+ * capacity, a non-finite density or velocity of a cell at the collision
+ * (non-finite PDFs), or |u_bar| > 0.1 in a cell (outside the low-Mach range
+ * of the equilibrium of Eq. LBM_EQ). The message names the conditions. */
 lbdem_status lbdem_sync(lbdem_domain_t h);
 
 /* Copy one field (FP64, [ncomp][Nc]) to host or device memory `out`

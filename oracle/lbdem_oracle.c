@@ -1086,7 +1086,18 @@ int orc_step(const orc_params *pin, orc_state *s, orc_aux *aux)
         if (eps[c] < mine) mine = eps[c];
     }
 
-    /* S3: GNS-LBM step */
+    /* S3: GNS-LBM step. Reading for the failure checks (the paper states no
+     * limits): besides non-finite values, a cell velocity
+     * u_bar = (j + f_acc/2)/rho of magnitude above 0.1 is flagged, beyond
+     * the low-Mach range in which the second-order equilibrium holds. */
+    for (int64_t c = 0; c < nc; ++c) {
+        double uu = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double ua = (j[a * nc + c] + 0.5 * facc[a * nc + c]) / rho[c];
+            uu += ua * ua;
+        }
+        if (!(uu <= 0.01)) status = 3;
+    }
     double *dfn = malloc(sizeof(double) * Q * (size_t)nc);
     orc_lbm_collide_stream(p, s->df, dfn, eps, facc);
     for (int64_t c = 0; c < Q * nc; ++c)

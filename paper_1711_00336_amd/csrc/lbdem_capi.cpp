@@ -43,6 +43,11 @@ struct Oom {
     size_t bytes;
 };
 
+// a request the explicit coupling cannot advance stably (LBDEM_E_UNSTABLE)
+struct Unstable : std::runtime_error {
+    using std::runtime_error::runtime_error;
+};
+
 }  // namespace
 
 struct lbdem_domain {
@@ -213,6 +218,8 @@ lbdem_status guarded(lbdem_domain_t h, F &&f)
         return fail(h, LBDEM_E_DEVICE, std::string(e.what) + ": " + hipGetErrorString(e.e));
     } catch (const Oom &o) {
         return fail(h, LBDEM_E_OOM, "device allocation of " + std::to_string(o.bytes) + " bytes failed");
+    } catch (const Unstable &e) {
+        return fail(h, LBDEM_E_UNSTABLE, e.what());
     } catch (const std::exception &e) {
         return fail(h, LBDEM_E_INVALID, e.what());
     }
@@ -555,6 +562,48 @@ void put_particles(lbdem_domain_t h, const HostParticles &hp)
     update_body_force(h, hp.d, hp.rho);
 }
 
+// Stability estimate of the explicit fluid-particle coupling. Over one
+// interaction subcycle the drag with F_const frozen relaxes the slip with
+// the particle response time tau_p = rho_p d^2 / (18 mu f(eps)) (Table 1
+// drag at Re -> 0, f the Tenneti factor, Stokes for eps = 0); the added
+// mass, evaluated with the previous subcycle's du_p/dt, lags by one
+// subcycle. The slip error then obeys lambda^2 - (1 - r - a) lambda - a = 0
+// with r = dt_int / tau_p and a = C_am rho_f / rho_p, whose roots stay
+// inside the unit circle only for r < 2 - 2a. The solid fraction in f is
+// eps_ref = max(V_max/8, <eps_p>): a lone sphere sees V/8 of itself through
+// the kernel, a suspension at least its mean solid fraction. Returns the
+// largest stable dt_int, min over particles of (2 - 2a) tau_p (infinity
+// without particles).
+double tenneti_stokes_factor(double ep)
+{
+    // Table 1 drag factor (1 - eps)^2 [1/(1-eps)^3 + 5.81 eps/(1-eps)^3
+    // + 0.48 eps^(1/3)/(1-eps)^4] at Re = 0
+    const double e1 = 1.0 - ep;
+    return e1 * e1 * ((1.0 + 5.81 * ep) / (e1 * e1 * e1) + 0.48 * std::cbrt(ep) / (e1 * e1 * e1 * e1));
+}
+
+double stable_dt_int(const lbdem_params &p, int64_t n, const double *d, const double *rho)
+{
+    if (n <= 0) return HUGE_VAL;
+    const double mu = p.rho_f * (p.tau - 0.5) / 3.0;
+    double vmax = 0.0, vsum = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double V = M_PI * d[i] * d[i] * d[i] / 6.0;
+        vmax = std::max(vmax, V);
+        vsum += V;
+    }
+    const double nc = (double)p.n[0] * p.n[1] * p.n[2];
+    const double eref = std::min(std::max(vmax / 8.0, vsum / nc), 0.99);
+    const double f = tenneti_stokes_factor(eref);
+    double dt = HUGE_VAL;
+    for (int64_t i = 0; i < n; ++i) {
+        const double taup = rho[i] * d[i] * d[i] / (18.0 * mu * f);
+        const double a = p.use_am ? p.c_am * p.rho_f / rho[i] : 0.0;
+        dt = std::min(dt, (2.0 - 2.0 * a) * taup);
+    }
+    return dt;
+}
+
 void check_particles(lbdem_domain_t h, int64_t n, const double *x, const double *d, const double *rho)
 {
     for (int64_t i = 0; i < n; ++i) {
@@ -744,6 +793,19 @@ lbdem_status lbdem_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)
     return LBDEM_OK;
 }
 
+lbdem_status lbdem_stability_limit(const lbdem_params *p, int64_t n, const double *d, const double *rho_p,
+                                   double *dt_int_max)
+{
+    if (!p || !dt_int_max || n < 0 || (n > 0 && (!d || !rho_p))) return fail(nullptr, LBDEM_E_INVALID, "null argument");
+    if (!(p->tau > 0.5) || !(p->rho_f > 0.0)) return fail(nullptr, LBDEM_E_INVALID, "tau must be > 1/2, rho_f > 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (!(d[i] > 0.0) || !(rho_p[i] > 0.0) || !std::isfinite(d[i]) || !std::isfinite(rho_p[i]))
+            return fail(nullptr, LBDEM_E_INVALID, "diameter and density must be > 0");
+    *dt_int_max = stable_dt_int(*p, n, d, rho_p);
+    const double dt = p->n_int >= 1 ? 1.0 / p->n_int : 1.0;
+    return dt < *dt_int_max ? LBDEM_OK : LBDEM_E_UNSTABLE;
+}
+
 lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_t *out)
 {
     if (!p || !out) return fail(nullptr, LBDEM_E_INVALID, "null argument");
@@ -860,6 +922,15 @@ lbdem_status lbdem_add_particles(lbdem_domain_t h, int64_t n, const double *x, c
         hip_check(hipStreamSynchronize(h->stream), "sync");
         HostParticles hp = fetch_particles(h);
         const int64_t n0 = h->pt.np;
+        {
+            std::vector<double> dd(hp.d), rr(hp.rho);
+            dd.insert(dd.end(), d, d + n);
+            rr.insert(rr.end(), rho_p, rho_p + n);
+            const double lim = stable_dt_int(h->prm, n0 + n, dd.data(), rr.data());
+            if (!(h->phys.dt_int < lim))
+                throw Unstable("explicit coupling estimated unstable: dt_int = " + std::to_string(h->phys.dt_int) +
+                               " >= (2 - 2a) tau_p = " + std::to_string(lim) + "; raise n_int");
+        }
         hp.x.insert(hp.x.end(), x, x + 3 * n);
         if (u) hp.u.insert(hp.u.end(), u, u + 3 * n); else hp.u.resize(3 * (n0 + n), 0.0);
         if (omega) hp.w.insert(hp.w.end(), omega, omega + 3 * n); else hp.w.resize(3 * (n0 + n), 0.0);
@@ -901,6 +972,8 @@ lbdem_status lbdem_sync(lbdem_domain_t h)
             if (fl & FLAG_NONFINITE) m += " non-finite particle state;";
             if (fl & FLAG_EPS) m += " fluid fraction <= 0;";
             if (fl & FLAG_NLIST) m += " more neighbours within the interaction reach than the list holds;";
+            if (fl & FLAG_FLUID_NONFINITE) m += " non-finite fluid state (PDFs);";
+            if (fl & FLAG_MACH) m += " fluid velocity |u| > 0.1 (lattice Mach number limit);";
             return fail(h, LBDEM_E_UNSTABLE, m);
         }
         return LBDEM_OK;

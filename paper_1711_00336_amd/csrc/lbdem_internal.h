@@ -124,7 +124,9 @@ enum : int {
     FLAG_SKIN = 2,              // moved more than the skin within a subcycle
     FLAG_NONFINITE = 4,
     FLAG_EPS = 8,               // eps_f <= 0
-    FLAG_NLIST = 16             // a particle has more list neighbours than the capacity nbr
+    FLAG_NLIST = 16,            // a particle has more list neighbours than the capacity nbr
+    FLAG_FLUID_NONFINITE = 32,  // non-finite density or velocity of a cell at the collision
+    FLAG_MACH = 64              // |u_bar| > 0.1 in a cell (beyond the low-Mach range of the LBM)
 };
 
 constexpr int kTimingClasses = 13;  // kernel classes of lbdem_kernel_time

@@ -1727,7 +1727,7 @@ __device__ __forceinline__ R relax_time(const Desc &D, R ep, R rho, const R f[19
 }
 
 template <typename R, bool VISC>
-__device__ __forceinline__ void collide_cell(const Desc &D, const Cells<R> &C, int64_t c, R post[19])
+__device__ __forceinline__ void collide_cell(const Desc &D, const Cells<R> &C, int64_t c, R post[19], int &bad)
 {
     const int64_t nc = D.g.nc;
     R f[19];
@@ -1749,6 +1749,10 @@ __device__ __forceinline__ void collide_cell(const Desc &D, const Cells<R> &C, i
     const R eps = one - C.epsp[c];
     const R ieps = one / eps;
     const R uu = ux * ux + uy * uy + uz * uz;
+    // non-finite PDFs make rho or u non-finite; |u| > 0.1 leaves the low-Mach
+    // range in which the equilibrium expansion holds
+    if (!isfinite(rho) || !isfinite(uu)) bad = FLAG_FLUID_NONFINITE;
+    else if (uu > (R)0.01) bad = FLAG_MACH;
     if (VISC) {
         R feq[19];
 #pragma unroll
@@ -1800,7 +1804,9 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(Desc D, Cells<R> C)
     int i, j, k;
     cell_coords(D.g, c, i, j, k);
     R post[19];
-    collide_cell<R, VISC>(D, C, c, post);
+    int bad = 0;
+    collide_cell<R, VISC>(D, C, c, post, bad);
+    if (bad) atomicOr(D.flags, bad);
     const bool wall_x = !D.g.per[0], wall_y = !D.g.per[1], wall_z = !D.g.per[2];
 #pragma unroll
     for (int q = 0; q < 19; ++q) {

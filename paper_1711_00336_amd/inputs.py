@@ -59,7 +59,7 @@ def uniform(seed: int, stream: int, start: int, n: int) -> np.ndarray:
 
 
 # streams
-_S_DIAM, _S_POS, _S_RHO, _S_DOMAIN, _S_PERTURB = 1, 2, 3, 4, 5
+_S_DIAM, _S_POS, _S_RHO, _S_DOMAIN, _S_PERTURB, _S_JITTER = 1, 2, 3, 4, 5, 6
 
 
 # ---------------------------------------------------------------------------
@@ -400,13 +400,19 @@ def case_dilute_periodic(seed=0, n=128, eps_p=0.05, d=0.8, precision="fp32dev"):
     return Case(f"periodic-{n}^3-eps{eps_p}", p, parts, seed)
 
 
+def dense_walled_params(n=(256, 256, 512), precision="fp32dev", n_dem=10, n_int=10):
+    """Parameters of the dense suspension: walls in z, tau = 0.7, gravity
+    1e-5 on the particles, restitution 0.9, lubrication cut-off 1.0."""
+    return Params(n=tuple(n), periodic=(1, 1, 0), tau=0.7, gravity=(0.0, 0.0, -1e-5),
+                  body_force_auto=0, e_n=0.9, mu_c=0.25, T_c=0.0, h_c=1.0,
+                  n_int=n_int, n_dem=n_dem, precision=precision)
+
+
 def case_dense_walled(seed=0, n=(256, 256, 512), eps_p=0.4, precision="fp32dev",
                       n_dem=10, n_int=10, progress=None):
     """Dense suspension: walls in z, d ~ U[0.9, 1.1], solid fraction 0.4,
     density ratio 2.5, restitution 0.9, lubrication with cut-off 1.0."""
-    p = Params(n=tuple(n), periodic=(1, 1, 0), tau=0.7, gravity=(0.0, 0.0, -1e-5),
-               body_force_auto=0, e_n=0.9, mu_c=0.25, T_c=0.0, h_c=1.0,
-               n_int=n_int, n_dem=n_dem, precision=precision)
+    p = dense_walled_params(n, precision, n_dem, n_int)
     parts = make_particles(seed, p, float(eps_p), 0.9, 1.1, 2.5, progress=progress)
     return Case(f"dense-{n[0]}x{n[1]}x{n[2]}-eps{eps_p}", p, parts, seed)
 
@@ -467,4 +473,12 @@ def perturbed_state(seed, ncells, amp=1e-6, n_fields=19):
     """Random PDF deviations of amplitude amp (for parity tests of the
     stream-collide away from rest). Zero-mean per cell is not enforced."""
     u = uniform(seed, _S_PERTURB, 0, n_fields * ncells).reshape(n_fields, ncells)
+    return amp * (2.0 * u - 1.0)
+
+
+def position_jitter(seed, n, amp):
+    """Independent uniform offsets in [-amp, amp) for n positions, (n, 3)
+    (a seeded perturbation of a packing, e.g. to measure how fast two
+    nearby trajectories separate)."""
+    u = uniform(seed, _S_JITTER, 0, 3 * n).reshape(n, 3)
     return amp * (2.0 * u - 1.0)

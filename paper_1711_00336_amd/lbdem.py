@@ -129,6 +129,8 @@ def lib():
             "lbdem_server_stats": (st, [H, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]),
             "lbdem_server_destroy": (st, [H]),
             "lbdem_kernel_time": (st, [H, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+            "lbdem_stability_limit": (st, [C.POINTER(lbdem_params), C.c_int64, C.c_void_p, C.c_void_p,
+                                           C.POINTER(C.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -168,6 +170,19 @@ def params_from(prm) -> lbdem_params:
     P.use_eilers = int(getattr(prm, "use_eilers", 0))
     P.use_les = int(getattr(prm, "use_les", 0))
     return P
+
+
+def lbdem_stability_limit(prm, d, rho_p):
+    """(status, largest stable interaction subcycle length) of the explicit
+    coupling estimate for these particles (host-only; no device needed)."""
+    P = params_from(prm)
+    d = np.ascontiguousarray(d, np.float64).reshape(-1)
+    rho_p = np.ascontiguousarray(rho_p, np.float64).reshape(-1)
+    out = C.c_double(0.0)
+    st = lib().lbdem_stability_limit(C.byref(P), len(d), _ptr(d), _ptr(rho_p), C.byref(out))
+    if st not in (OK, E_UNSTABLE):
+        _check(None, st)
+    return st, out.value
 
 
 class Domain:

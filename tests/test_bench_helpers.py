@@ -65,10 +65,30 @@ def test_kernel_bytes_per_unit_figures(bench):
     nc, n = 16 * 8 * 4, 10
     kb = bench.kernel_bytes(case, 4.0)
     assert kb["stream_collide"] == nc * 42 * 4
-    assert kb["gather_eps"] == nc * 11 * 4 + n * 104
+    # FP32 form: weights stored as 4-byte floats
+    assert kb["gather_eps"] == nc * 11 * 4 + n * (36 + 32)
     assert kb["dem_force"] == n * (140 + 16)
-    assert kb["part_am"] == n * 140 + nc * 3 * 4
+    assert kb["part_am"] == n * (76 + 36) + nc * 3 * 4
+    assert kb["part_drag"] == n * (128 + 36) + nc * 7 * 4
+    assert kb["bins"] == n * (300 + 36 + 64) + nc * 20
     lift = bench.kernel_bytes(I.Case("t", prm.copy(use_lift=1), parts, 0), 4.0)
-    assert lift["part_am"] == n * 188 + nc * 9 * 4 and lift["curl"] == nc * 6 * 4
+    assert lift["part_am"] == n * (124 + 36) + nc * 9 * 4 and lift["curl"] == nc * 6 * 4
     fp64 = bench.kernel_bytes(I.Case("t", prm.copy(precision="fp64"), parts, 0), 4.0)
     assert fp64["stream_collide"] == 2 * kb["stream_collide"]
+    # FP64 weights, no packed DEM records
+    assert fp64["part_drag"] == n * 200 + nc * 7 * 8
+    assert fp64["bins"] == n * (300 + 72) + nc * 20
+
+
+def test_dem_roofline_counts_pair_flops(bench):
+    """The DEM force pass is rated against the FP64 vector peak with 150
+    flops per pair evaluation within reach; other classes against HBM."""
+    times = {"dem_force": {"ms_per_step": 2.0, "launches_per_step": 2.0, "avg_launch_ms": 1.0},
+             "integrate": {"ms_per_step": 1.0, "launches_per_step": 2.0, "avg_launch_ms": 0.5}}
+    kb = {"dem_force": 4_000_000, "integrate": 8_000_000}
+    r = bench.roofline_entry("dem_force", times, kb, "none", None, 1e9)
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s"
+    assert r["achieved"] == pytest.approx(150e9 / 1e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / 78.6, rel=1e-3)
+    h = bench.roofline_entry("integrate", times, kb, "none", None, 1e9)
+    assert h["bound"] == "hbm" and h["achieved"] == pytest.approx(8e6 / 0.5e-3 / 1e9)

