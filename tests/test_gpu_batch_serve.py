@@ -28,7 +28,7 @@ def _cases():
     p = I.Params(n=(24, 20, 28), periodic=(1, 1, 0), tau=0.8, n_int=3, h_c=0.5, precision="fp64")
     out.append(I.Case("walled-fp64", p, I.make_particles(1, p, 40, 0.5, 0.7, 2.5), 1))
     out.append(I.case_settling(2, 20, 0.1, 0.8, 2.5, precision="fp32dev"))
-    c = I.case_settling(3, 16, 0.3, 0.8, 1.5, precision="fp64", n_int=5)
+    c = I.case_settling(3, 16, 0.3, 0.8, 1.5, precision="fp64", n_int=5, tau=I.SWEEP_TAU)
     out.append(c)
     p = I.Params(n=(30, 18, 22), periodic=(1, 1, 0), tau=0.7, n_int=4, h_c=0.9, precision="fp32dev")
     out.append(I.Case("walled-fp32", p, I.make_particles(4, p, 0.05, 0.8, 0.9, 3.0), 4))
