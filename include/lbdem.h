@@ -223,6 +223,20 @@ lbdem_status lbdem_read_particle_lift(lbdem_domain_t h, double *F_l);
 /* FP64 reductions of the current state (Sec. 4.1 settling velocity). */
 lbdem_status lbdem_diagnostics(lbdem_domain_t h, lbdem_diag *out);
 
+/* The same reductions, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no device allocation at all. The per-block partials and the
+ * final values live in a static device array of 12 x 1024 + 16 doubles
+ * (98.4 KB) that each device holds for the life of the process; its device
+ * address is looked up once per device on the first call there. Results
+ * equal lbdem_diagnostics exactly (same kernels, same summation order).
+ * All calls on one device share the array: calls that overlap in time on
+ * one device (different threads or streams) race and must be serialised by
+ * the caller. E_INVALID if the reduction would need more than 1024 blocks
+ * of partials (the launch caps it at 1024, so this does not happen),
+ * E_DEVICE if the array's address cannot be found. */
+lbdem_status lbdem_diagnostics_noalloc(lbdem_domain_t h, lbdem_diag *out);
+
 int64_t lbdem_num_cells(lbdem_domain_t h);
 int64_t lbdem_num_particles(lbdem_domain_t h);
 

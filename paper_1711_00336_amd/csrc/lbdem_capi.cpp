@@ -56,6 +56,7 @@ struct lbdem_domain {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int prec = LBDEM_FP64;
+    int device = 0;             // the HIP device current at creation
     Geo geo{};
     Phys phys{};
     Tune tune{-1};
@@ -837,6 +838,7 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
     set_fastdiv((uint32_t)p->n[0] * (uint32_t)p->n[1], h->geo.mxy, h->geo.sxy);
     resolve_phys(h);
     lbdem_status st = guarded(nullptr, [&]() -> lbdem_status {
+        hip_check(hipGetDevice(&h->device), "hipGetDevice");
         if (hip_stream) h->stream = (hipStream_t)hip_stream;
         else {
             hip_check(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking), "hipStreamCreate");
@@ -1061,6 +1063,57 @@ lbdem_status lbdem_diagnostics(lbdem_domain_t h, lbdem_diag *out)
         hip_check(hipGetLastError(), "diag");
         double v[12];
         hip_check(hipMemcpyAsync(v, h->diag_out, sizeof(v), hipMemcpyDeviceToHost, h->stream), "diag copy");
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        const double nc = (double)h->geo.nc, np = (double)h->pt.np;
+        out->mass_dev = v[0];
+        for (int a = 0; a < 3; ++a) {
+            out->mom_fluid[a] = v[1 + a];
+            out->mom_part[a] = v[8 + a];
+        }
+        out->mean_eps_f = v[4] / nc;
+        out->min_eps_f = v[5];
+        out->u_ps = (np > 0 ? v[11] / np : 0.0) - v[6] / nc;
+        out->max_u = v[7];
+        out->step = h->step_host;
+        out->np = h->pt.np;
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_diagnostics_noalloc(lbdem_domain_t h, lbdem_diag *out)
+{
+    if (!h || !out) return fail(h, LBDEM_E_INVALID, "null argument");
+    return guarded(h, [&]() -> lbdem_status {
+        int cur = -1;
+        hip_check(hipGetDevice(&cur), "hipGetDevice");
+        if (cur != h->device) hip_check(hipSetDevice(h->device), "hipSetDevice");
+        struct Restore {
+            int dev;
+            bool on;
+            ~Restore()
+            {
+                if (on) (void)hipSetDevice(dev);
+            }
+        } restore{cur, cur != h->device};
+        double *sc = diag_scratch_on_device(h->device);
+        if (!sc) throw HipError{hipErrorInvalidSymbol, "looking up the diagnostics scratch"};
+        Desc D = h->desc();
+        const int nb = diag_blocks(D);
+        if ((int64_t)nb * kDiagValues + 16 > kDiagScratchDoubles)
+            throw std::runtime_error("diagnostics reduction of " + std::to_string(nb) +
+                                     " blocks exceeds the static scratch of " +
+                                     std::to_string(kDiagMaxBlocks) + " blocks");
+        double *part = sc, *res = sc + (int64_t)nb * kDiagValues;
+        if (h->prec == LBDEM_FP64) {
+            Cells<double> C = h->cells<double>();
+            launch_diag<double>(D, C, C.df_src, part, nb, res, h->stream);
+        } else {
+            Cells<float> C = h->cells<float>();
+            launch_diag<float>(D, C, C.df_src, part, nb, res, h->stream);
+        }
+        hip_check(hipGetLastError(), "diag");
+        double v[kDiagValues];
+        hip_check(hipMemcpyAsync(v, res, sizeof(v), hipMemcpyDeviceToHost, h->stream), "diag copy");
         hip_check(hipStreamSynchronize(h->stream), "sync");
         const double nc = (double)h->geo.nc, np = (double)h->pt.np;
         out->mass_dev = v[0];

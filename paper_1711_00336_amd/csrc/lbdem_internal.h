@@ -157,6 +157,13 @@ template <typename R>
 void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials, int nblk, double *out,
                  hipStream_t s);
 int diag_blocks(const Desc &D);
+// the diagnostics reduction: 12 values, at most 1024 blocks of partials
+constexpr int kDiagValues = 12;
+constexpr int kDiagMaxBlocks = 1024;
+constexpr int64_t kDiagScratchDoubles = (int64_t)kDiagValues * kDiagMaxBlocks + 16;
+// Device address of the static diagnostics scratch on `device` (looked up
+// once per device, with that device current); nullptr if the lookup fails.
+double *diag_scratch_on_device(int device);
 
 void launch_dem_force(const Desc &D, hipStream_t s);
 void launch_nlist(const Desc &D, hipStream_t s);      // rebuild Verlet lists if flagged

@@ -10,6 +10,8 @@
 // is deterministic and needs no floating-point atomics.
 #include "lbdem_internal.h"
 
+#include <mutex>
+
 #include <cmath>
 
 namespace lbdem {
@@ -1831,7 +1833,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_collide(Desc D, Cells<R> C)
 // per-block partials: [0] sum drho, [1..3] sum j, [4] sum eps, [5] min eps,
 // [6] sum u_f,z, [7] max |u_bar|, [8..10] sum m u, [11] sum u_z
 // ---------------------------------------------------------------------------
-constexpr int kDiag = 12;
+constexpr int kDiag = kDiagValues;
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_diag(Desc D, Cells<R> C, const R *df, double *part)
@@ -2092,8 +2094,33 @@ int diag_blocks(const Desc &D)
 {
     int64_t n = D.g.nc > D.pt.np ? D.g.nc : D.pt.np;
     int64_t b = (n + kBlock - 1) / kBlock;
-    if (b > 1024) b = 1024;
+    if (b > kDiagMaxBlocks) b = kDiagMaxBlocks;
     return (int)(b < 1 ? 1 : b);
+}
+
+// Scratch of the allocation-free diagnostics (lbdem_diagnostics_noalloc):
+// the per-block partials and the final values of k_diag / k_diag_final,
+// 12 x 1024 + 16 doubles (98.4 KB), one copy per device for the life of the
+// process. Host code never names the array itself (on the host it is only a
+// stand-in): it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device with that device current.
+static __device__ __align__(256) double scratch[kDiagScratchDoubles];
+
+double *diag_scratch_on_device(int device)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static double *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess || cur != device) return nullptr;
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        addr[device] = static_cast<double *>(p);
+    }
+    return addr[device];
 }
 template <typename R>
 void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials, int nblk, double *out,

@@ -105,6 +105,7 @@ def lib():
             "lbdem_read_particle_forces": (st, [H] + [C.c_void_p] * 4),
             "lbdem_read_particle_lift": (st, [H, C.c_void_p]),
             "lbdem_diagnostics": (st, [H, C.POINTER(lbdem_diag)]),
+            "lbdem_diagnostics_noalloc": (st, [H, C.POINTER(lbdem_diag)]),
             "lbdem_num_cells": (C.c_int64, [H]),
             "lbdem_num_particles": (C.c_int64, [H]),
             "lbdem_get_state": (st, [H, C.POINTER(lbdem_state_view)]),
@@ -273,6 +274,13 @@ class Domain:
     def lbdem_diagnostics(self):
         D = lbdem_diag()
         _check(self.h, lib().lbdem_diagnostics(self.h, C.byref(D)))
+        return dict(mass_dev=D.mass_dev, mom_fluid=np.array(D.mom_fluid[:]), mom_part=np.array(D.mom_part[:]),
+                    u_ps=D.u_ps, mean_eps_f=D.mean_eps_f, min_eps_f=D.min_eps_f, max_u=D.max_u,
+                    step=D.step, np=D.np)
+
+    def lbdem_diagnostics_noalloc(self):
+        D = lbdem_diag()
+        _check(self.h, lib().lbdem_diagnostics_noalloc(self.h, C.byref(D)))
         return dict(mass_dev=D.mass_dev, mom_fluid=np.array(D.mom_fluid[:]), mom_part=np.array(D.mom_part[:]),
                     u_ps=D.u_ps, mean_eps_f=D.mean_eps_f, min_eps_f=D.min_eps_f, max_u=D.max_u,
                     step=D.step, np=D.np)
