@@ -11,13 +11,10 @@ settling workload shape after 200 coupled steps from rest:
 and, for one step from an identical state, every state array within 1e-5 of
 its largest oracle value (FP32 rounding of O(1e-7) deviations).
 
-The total momentum of a periodic settling box is the small residual of the
-fluid body force and the particles' submerged weight (Sec. 4.1 Setup). The
-FP32 collision rounds nearly the same PDF values the same way in every cell
-of a nearly uniform flow, so its rounding error adds up coherently over the
-cells and steps instead of averaging out: the error grows with the momentum
-injected by the body force, not with the residual, and TOL_MOM states the
-bound this form reaches on the scale above.
+The momentum scale is that of the FP32 tolerances: the particles' and the
+fluid's momentum magnitudes, not the net momentum, which in a periodic
+settling box is only the small residual of the fluid body force and the
+particles' submerged weight (Sec. 4.1 Setup). Measured on MI355X: 4.4e-7.
 """
 import numpy as np
 import pytest
@@ -29,7 +26,7 @@ from tests.parity_util import compare_states, load_oracle_state, warm_oracle
 pytestmark = pytest.mark.gpu
 
 TOL32_STEP = 1e-5
-TOL_UPS, TOL_EPS, TOL_MOM = 1e-3, 1e-6, 1e-3
+TOL_UPS, TOL_EPS, TOL_MOM = 1e-3, 1e-6, 1e-6
 
 
 @pytest.fixture(scope="module")
