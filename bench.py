@@ -112,7 +112,7 @@ def mean_list_length(case, vskin=0.25, max_query=100000):
     return len(I_) / len(q)
 
 
-def kernel_bytes(case, nlist):
+def kernel_bytes(case, nlist, dem_order=0):
     """Algorithmic HBM bytes per launch of each timed kernel class: what the
     operation must read and write once (re-reads of neighbour cells or
     particles, which a cache can serve, are not counted). rs is the cell
@@ -148,7 +148,9 @@ def kernel_bytes(case, nlist):
                       permutation of x, u, omega, a, d, rho, id, label
                       (2 x 120 B), new stencil (12 B + 9 ws) and, in the
                       FP32 form, the 64-byte DEM record; per cell count,
-                      scan and offsets (20 B)     (300 + 9 ws [+ 64]) B + 20 B
+                      scan and offsets (20 B); with the blocked DEM order
+                      also its slot list (4 B per particle)
+                                             (300 + 9 ws [+ 64] [+ 4]) B + 20 B
       curl (lift)     per cell u_f read, curl written (the subcycle's u_f is
                       evaluated by the moments pass and the volume-fraction
                       gather)                                            6 rs
@@ -166,7 +168,8 @@ def kernel_bytes(case, nlist):
             "gather_fd": nc * 10 * rs + n * (9 * ws + 24),
             "gather_eps": nc * 11 * rs + n * (9 * ws + 32), "nlist": 0,
             "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * 256,
-            "bins": n * (300 + 9 * ws + (64 if fp32 else 0)) + nc * 20, "curl": nc * 6 * rs}
+            "bins": n * (300 + 9 * ws + (64 if fp32 else 0) + (4 if dem_order else 0)) + nc * 20,
+            "curl": nc * 6 * rs}
 
 
 # DEM pair arithmetic (a8): about 150 FP64 flops per pair evaluation within
@@ -485,7 +488,8 @@ def run_step_workload(lbdem, torch, case, wl_name, K, W, ksteps, stream, args):
         print(f"[bench] {case.particles.n} particles resident", file=sys.stderr, flush=True)
         nc = dom.nc
         variant = dom.lbdem_autotune()
-        print(f"[bench] autotuned gather variant {variant}", file=sys.stderr, flush=True)
+        tuning = dom.lbdem_get_tuning()
+        print(f"[bench] autotuned: {tuning}", file=sys.stderr, flush=True)
         dom.lbdem_step(W)
         dom.lbdem_sync()
         torch.cuda.synchronize()
@@ -514,14 +518,15 @@ def run_step_workload(lbdem, torch, case, wl_name, K, W, ksteps, stream, args):
     nreach = mean_list_length(case, vskin=0.0)
     print(f"[bench] mean Verlet-list length {nlist:.2f}, neighbours within reach {nreach:.2f}",
           file=sys.stderr, flush=True)
-    kb = kernel_bytes(case, nlist)
+    dem_order = tuning["dem_order"] if tuning["dem_order"] >= 0 else int(case.particles.n >= 1 << 20)
+    kb = kernel_bytes(case, nlist, dem_order)
     npairs = nreach * case.particles.n
     roofs = {k: roofline_entry(k, times, kb, wl_name, variant, npairs) for k in times
              if times[k]["launches_per_step"] > 0}
     roofs = {k: v for k, v in roofs.items() if v is not None}
     dom_cls = max(roofs, key=lambda k: times[k]["ms_per_step"])
     return dict(nc=nc, dt=dt, variant=variant, times=times, roofs=roofs, dominant=dom_cls, diag=diag,
-                nlist=nlist, nreach=nreach)
+                nlist=nlist, nreach=nreach, tuning=dict(tuning, dem_order_resolved=dem_order))
 
 
 def main():
@@ -635,6 +640,7 @@ def main():
                    "n_int": case.params.n_int, "n_dem": case.params.n_dem,
                    "pdf_storage": "f32 deviation" if case.params.precision == "fp32dev" else "f64 deviation",
                    "particle_integration": "f64", "tau": case.params.tau, "gather_variant": r["variant"],
+                   "dem_order": r["tuning"]["dem_order_resolved"], "dem_block": list(r["tuning"]["dem_block"]),
                    "lift": bool(args.lift), "eilers_les": bool(args.visc),
                    "mean_list_length": round(r["nlist"], 2), "neighbours_within_reach": round(r["nreach"], 2)},
         "roofline": roofs[r["dominant"]],

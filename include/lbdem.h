@@ -199,7 +199,10 @@ lbdem_status lbdem_step(lbdem_domain_t h, int64_t nsteps);
  * search skin within a subcycle, eps_f <= 0, more list neighbours than the
  * capacity, a non-finite density or velocity of a cell at the collision
  * (non-finite PDFs), or |u_bar| > 0.1 in a cell (outside the low-Mach range
- * of the equilibrium of Eq. LBM_EQ). The message names the conditions. */
+ * of the equilibrium of Eq. LBM_EQ). The message names the conditions.
+ * The flags are sticky: once set, later steps skip the particle binning and
+ * neighbour search (the state is no longer meaningful), lbdem_add_particles
+ * returns E_STATE, and only lbdem_set_state / lbdem_load_state clear them. */
 lbdem_status lbdem_sync(lbdem_domain_t h);
 
 /* Copy one field (FP64, [ncomp][Nc]) to host or device memory `out`
@@ -268,11 +271,30 @@ lbdem_status lbdem_load_state(lbdem_domain_t h, const void *blob, size_t size);
 lbdem_status lbdem_set_timing(lbdem_domain_t h, int on);
 lbdem_status lbdem_kernel_time(lbdem_domain_t h, int cls, double *ms_total, int64_t *launches);
 
-/* Pick launch shapes for this domain by timing them on its current state
- * (the gather variant; results are bit-identical across choices, since every
- * variant sums a cell's particles in the same order). Optional out: the
- * chosen variant, as for lbdem_set_gather_variant. */
+/* Pick launch shapes for this domain by timing them on its current state:
+ * the gather variant (see lbdem_set_gather_variant) and the processing order
+ * of the DEM force pass (slot order, or block by block with one of a few
+ * block shapes, so that the particles in flight on one XCD cover a compact
+ * region whose neighbours stay in its L2 cache). Results are bit-identical
+ * across choices: every gather variant sums a cell's particles in the same
+ * order, and each particle's DEM force is the same in any processing order.
+ * Optional out: the chosen gather variant. */
 lbdem_status lbdem_autotune(lbdem_domain_t h, int32_t *gather_variant);
+
+/* Launch choices of a domain (autotuned or set by hand). */
+typedef struct lbdem_tuning {
+    int32_t gather_variant;   /* as lbdem_set_gather_variant; -1 automatic by density */
+    int32_t dem_order;        /* DEM force pass: -1 automatic (blocked from 2^20
+                                 particles on), 0 slot order, 1 blocked order */
+    int32_t dem_block[3];     /* block shape of the blocked order in cells, 1..256 each
+                                 (default 32 x 32 x 32) */
+} lbdem_tuning;
+
+/* Read the domain's launch choices. */
+lbdem_status lbdem_get_tuning(lbdem_domain_t h, lbdem_tuning *out);
+
+/* Set them (E_INVALID for values out of range). Synchronous. */
+lbdem_status lbdem_set_tuning(lbdem_domain_t h, const lbdem_tuning *t);
 
 /* Fix the gather variant (the launch shape of the particle-to-cell sums of
  * the volume fraction and the spread forces): -1 automatic by particle

@@ -59,7 +59,7 @@ struct lbdem_domain {
     int device = 0;             // the HIP device current at creation
     Geo geo{};
     Phys phys{};
-    Tune tune{-1};
+    Tune tune{-1, -1};
     int64_t version = 0;        // bumped whenever the particle set is replaced
     std::string err;
     int64_t step_host = 0;
@@ -74,6 +74,9 @@ struct lbdem_domain {
     int *cnt = nullptr, *start = nullptr, *list = nullptr, *bsum = nullptr, *loc = nullptr;
     int64_t list_cap = 0;
     int64_t nlist_rows = 0;     // particle rows the Verlet-list buffer holds
+    // blocked processing order of the DEM force pass
+    Order ord{};
+    int64_t ord_rows_cap = 0;
     // particles
     Parts pt{};
     double dmax = 0.0;
@@ -151,6 +154,9 @@ struct lbdem_domain {
         D.t = tune;
         D.b = Bins{cnt, start, list, bsum, loc};
         D.pt = pt;
+        D.o = ord;
+        // default: the blocked order once the particles outgrow the caches
+        D.t.dem_order = tune.dem_order >= 0 ? tune.dem_order : (pt.np >= (int64_t)1 << 20 ? 1 : 0);
         D.flags = flags;
         D.stepc = stepc;
         return D;
@@ -313,6 +319,27 @@ void update_search(lbdem_domain_t h)
 // Verlet-list capacity per particle: twice the mean number of neighbours
 // within the list reach (d_max + h_c + skin) at the domain's mean particle
 // density, plus 24; a particle with more neighbours raises FLAG_NLIST
+// block shape of the DEM processing order; (re)allocates the row arrays
+void set_order_shape(lbdem_domain_t h, int bx, int by, int bz)
+{
+    Order &O = h->ord;
+    const int ob[3] = {bx, by, bz};
+    int64_t rows = (int64_t)ob[1] * ob[2];
+    for (int a = 0; a < 3; ++a) {
+        O.ob[a] = ob[a];
+        O.nb[a] = (h->geo.n[a] + ob[a] - 1) / ob[a];
+        rows *= O.nb[a];
+    }
+    O.nrows = rows;
+    if (rows > h->ord_rows_cap) {
+        h->dfree(O.rowoff);
+        h->dfree(O.rowsum);
+        O.rowoff = (int *)h->dalloc(sizeof(int) * (size_t)rows);
+        O.rowsum = (int *)h->dalloc(sizeof(int) * (size_t)(rows / kScanPerBlock + 2));
+        h->ord_rows_cap = rows;
+    }
+}
+
 void ensure_lists(lbdem_domain_t h)
 {
     Parts &P = h->pt;
@@ -361,6 +388,7 @@ void sort_particles(lbdem_domain_t h)
     launch_bin_build(h->desc(), h->stream);
     launch_sort_permute(h->desc(), h->stream);
     swap_particle_buffers(h);
+    launch_dem_order(h->desc(), h->stream);
 }
 
 // the same, and the next subcycle's added-mass force of every particle
@@ -370,6 +398,7 @@ void sort_particles_am(lbdem_domain_t h)
     launch_bin_build(h->desc(), h->stream);
     launch_sort_permute_am<R>(h->desc(), h->cells<R>(), h->stream);
     swap_particle_buffers(h);
+    launch_dem_order(h->desc(), h->stream);
 }
 
 template <typename R>
@@ -459,6 +488,9 @@ void alloc_particles(lbdem_domain_t h, int64_t cap)
         hip_check(hipMemsetAsync(P.pk, 0, sizeof(DemRec) * c, h->stream), "hipMemsetAsync");
         hip_check(hipMemsetAsync(P.pk2, 0, sizeof(DemRec) * c, h->stream), "hipMemsetAsync");
     }
+    h->dfree(h->ord.porder);
+    h->ord.porder = (int *)h->dalloc(sizeof(int) * c);
+    hip_check(hipMemsetAsync(h->ord.porder, 0, sizeof(int) * c, h->stream), "hipMemsetAsync");
 }
 
 // host AoS [n][3] <-> device SoA [3][cap]
@@ -880,6 +912,7 @@ lbdem_status lbdem_create(const lbdem_params *p, void *hip_stream, lbdem_domain_
         hip_check(hipMemsetAsync(h->start, 0, sizeof(int) * (nc + 1), h->stream), "memset");
         hip_check(hipMemsetAsync(h->flags, 0, sizeof(int) * 4, h->stream), "memset");
         hip_check(hipMemsetAsync(h->stepc, 0, sizeof(long long) * 2, h->stream), "memset");
+        set_order_shape(h, 32, 32, 32);
         alloc_particles(h, 64);
         h->pt.np = 0;
         update_search(h);
@@ -922,6 +955,9 @@ lbdem_status lbdem_add_particles(lbdem_domain_t h, int64_t n, const double *x, c
         check_particles(h, n, x, d, rho_p);
         if (h->pt.np + n > ((int64_t)1 << 31) - 1) throw std::runtime_error("too many particles");
         hip_check(hipStreamSynchronize(h->stream), "sync");
+        int fl = 0;
+        hip_check(hipMemcpy(&fl, h->flags, sizeof(int), hipMemcpyDeviceToHost), "flags");
+        if (fl) return fail(h, LBDEM_E_STATE, "the domain has flagged instability; restore a state first");
         HostParticles hp = fetch_particles(h);
         const int64_t n0 = h->pt.np;
         {
@@ -1313,6 +1349,44 @@ static void autotune_impl(lbdem_domain_t h)
     for (int v = 0; v < kGatherVariants; ++v)
         if (t[v] < 0.97f * t[best_v]) best_v = v;
     h->tune.gather = best_v;
+
+    // DEM force pass: slot order against the blocked order with a few block
+    // shapes (each particle's force is the same in every order). The lists
+    // are brought up to date first, as the pass assumes.
+    if (h->pt.np > 0) {
+        launch_nlist(h->desc(), h->stream);
+        struct Cand {
+            int order, bx, by, bz;
+        };
+        const Cand cand[] = {{0, 32, 32, 32}, {1, 32, 32, 32}, {1, 64, 16, 16}, {1, 16, 16, 16}, {1, 32, 16, 8}};
+        float best_t = 1e30f;
+        Cand best = cand[0];
+        for (const Cand &c : cand) {
+            h->tune.dem_order = c.order;
+            if (c.order) set_order_shape(h, c.bx, c.by, c.bz);
+            launch_dem_order(h->desc(), h->stream);
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 4; ++rep) {
+                hip_check(hipEventRecord(a, h->stream), "hipEventRecord");
+                launch_dem_force(h->desc(), h->stream);
+                hip_check(hipEventRecord(b, h->stream), "hipEventRecord");
+                hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+                if (rep > 0) tmin = std::min(tmin, ms);
+            }
+            // a later candidate must be at least 3 % faster to replace the
+            // current best (near-equal timings flip from run to run)
+            if (tmin < 0.97f * best_t) {
+                best_t = tmin;
+                best = c;
+            }
+        }
+        h->tune.dem_order = best.order;
+        set_order_shape(h, best.bx, best.by, best.bz);
+        launch_dem_order(h->desc(), h->stream);
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     h->drop_graphs();
@@ -1328,6 +1402,36 @@ lbdem_status lbdem_autotune(lbdem_domain_t h, int32_t *gather_variant)
         if (h->prec == LBDEM_FP64) autotune_impl<double>(h);
         else autotune_impl<float>(h);
         if (gather_variant) *gather_variant = h->tune.gather;
+        return LBDEM_OK;
+    });
+}
+
+lbdem_status lbdem_get_tuning(lbdem_domain_t h, lbdem_tuning *out)
+{
+    if (!h || !out) return fail(h, LBDEM_E_INVALID, "null argument");
+    out->gather_variant = h->tune.gather;
+    out->dem_order = h->tune.dem_order;
+    for (int a = 0; a < 3; ++a) out->dem_block[a] = h->ord.ob[a];
+    return LBDEM_OK;
+}
+
+lbdem_status lbdem_set_tuning(lbdem_domain_t h, const lbdem_tuning *t)
+{
+    if (!h || !t) return fail(h, LBDEM_E_INVALID, "null argument");
+    if (t->gather_variant < -1 || t->gather_variant >= kGatherVariants)
+        return fail(h, LBDEM_E_INVALID, "unknown gather variant");
+    if (t->dem_order < -1 || t->dem_order > 1) return fail(h, LBDEM_E_INVALID, "dem_order must be -1, 0 or 1");
+    for (int a = 0; a < 3; ++a)
+        if (t->dem_block[a] < 1 || t->dem_block[a] > 256)
+            return fail(h, LBDEM_E_INVALID, "DEM block edges must be in 1..256 cells");
+    return guarded(h, [&]() -> lbdem_status {
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        h->tune.gather = t->gather_variant;
+        h->tune.dem_order = t->dem_order;
+        set_order_shape(h, t->dem_block[0], t->dem_block[1], t->dem_block[2]);
+        launch_dem_order(h->desc(), h->stream);
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+        h->drop_graphs();
         return LBDEM_OK;
     });
 }

@@ -107,6 +107,23 @@ struct Parts {
 // launch choices picked per domain (autotuner); -1 = heuristic default
 struct Tune {
     int gather;                 // -1 by density; 0/1/2/4 LDS tiles 16x4x8, 16x4x4, 8x4x4, 16x4x16; 3 per cell
+    int dem_order;              // 0: DEM force pass in slot order; 1: in the blocked order of Order
+};
+
+// Processing order of the DEM force pass. Slots are sorted by cell in
+// row-major order, so a run of consecutive slots is a thin slab of rows
+// whose neighbours reach two planes up and down. In the blocked order the
+// particles are visited block by block (blocks of ob[0] x ob[1] x ob[2]
+// cells, each block row by row), so the workgroups in flight on one XCD
+// cover a compact region and their neighbours' records stay in its L2.
+// Each particle's force is the same whatever the order.
+struct Order {
+    int *porder;                // [cap] slot of the v-th particle in blocked order
+    int *rowoff;                // [nrows] particles per block row, then their block-local exclusive prefix
+    int *rowsum;                // [nrows / kScanPerBlock + 2] scan block sums, then their exclusive prefix
+    int64_t nrows;              // block rows: blocks per axis (padded) x ob[1] x ob[2]
+    int ob[3];                  // block shape in cells
+    int nb[3];                  // blocks per axis, ceil(n / ob)
 };
 
 struct Desc {
@@ -115,6 +132,7 @@ struct Desc {
     Tune t;
     Bins b;
     Parts pt;
+    Order o;
     int *flags;                 // error bits
     long long *stepc;           // device step counter
 };
@@ -166,6 +184,7 @@ constexpr int64_t kDiagScratchDoubles = (int64_t)kDiagValues * kDiagMaxBlocks + 
 double *diag_scratch_on_device(int device);
 
 void launch_dem_force(const Desc &D, hipStream_t s);
+void launch_dem_order(const Desc &D, hipStream_t s);   // blocked processing order of the current slots
 void launch_nlist(const Desc &D, hipStream_t s);      // rebuild Verlet lists if flagged
 void launch_integrate(const Desc &D, int last_substep, hipStream_t s);
 void launch_bin_count(const Desc &D, hipStream_t s);

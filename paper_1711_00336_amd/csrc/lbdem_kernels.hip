@@ -1279,6 +1279,14 @@ template <typename T, bool REC> __device__ __forceinline__ void load_particle(co
     else load_pv(P, i, v);
 }
 
+// Once a step has flagged instability (non-finite or runaway particles),
+// the domain's state is no longer meaningful and is reported at the next
+// sync. The binning and neighbour-search kernels then do nothing: positions
+// that are no longer finite all clamp into one cell, and sorting or
+// scanning such a bin would take time quadratic in the particle count.
+// (These kernels have no barriers, so a per-thread check is safe.)
+__device__ __forceinline__ bool halted(const Desc &D) { return *(volatile const int *)D.flags != 0; }
+
 __device__ __forceinline__ void min_image(const Geo &g, double dx[3])
 {
 #pragma unroll
@@ -1298,7 +1306,7 @@ __device__ __forceinline__ void min_image(const Geo &g, double dx[3])
 __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
 {
     const Parts &P = D.pt;
-    if (*P.need == 0) return;
+    if (*P.need == 0 || halted(D)) return;
     const int64_t i = gidx();
     if (i >= P.np) return;
     const int64_t cap = P.cap;
@@ -1370,9 +1378,10 @@ template <typename T, bool REC>
 __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
 {
     const Parts &P = D.pt;
-    const int64_t i = gidx();
-    if (i == 0) *P.need = 0;  // lists are current for this subcycle
-    if (i >= P.np) return;
+    const int64_t v = gidx();
+    if (v == 0) *P.need = 0;  // lists are current for this subcycle
+    if (v >= P.np) return;
+    const int64_t i = D.t.dem_order ? (int64_t)D.o.porder[v] : v;
     PV<T> pi;
     load_particle<T, REC>(P, i, pi);
     T F[3] = {(T)0, (T)0, (T)0}, Tq[3] = {(T)0, (T)0, (T)0};
@@ -1405,6 +1414,82 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
         P.Fdem[a * cap + i] = (double)F[a];
         P.Tdem[a * cap + i] = (double)Tq[a];
     }
+}
+
+// Blocked processing order of the DEM force pass (see Order): block row r
+// = (block, lz, ly) with blocks row-major over the domain and rows y-fastest
+// inside a block; its cells are x0 <= x < x1 of row (y, z). Rows of the
+// padded last blocks that fall outside the domain are empty.
+__device__ __forceinline__ bool order_row(const Desc &D, int64_t r, int &x0, int &x1, int &y, int &z)
+{
+    const Order &O = D.o;
+    const int64_t per = (int64_t)O.ob[1] * O.ob[2];
+    const int64_t blk = r / per, lr = r - blk * per;
+    const int ly = (int)(lr % O.ob[1]), lz = (int)(lr / O.ob[1]);
+    const int bxi = (int)(blk % O.nb[0]);
+    const int byi = (int)((blk / O.nb[0]) % O.nb[1]);
+    const int bzi = (int)(blk / ((int64_t)O.nb[0] * O.nb[1]));
+    y = byi * O.ob[1] + ly;
+    z = bzi * O.ob[2] + lz;
+    x0 = bxi * O.ob[0];
+    x1 = min(x0 + O.ob[0], D.g.n[0]);
+    return y < D.g.n[1] && z < D.g.n[2];
+}
+
+__device__ __forceinline__ int order_row_count(const Desc &D, int x0, int x1, int y, int z, int &s0)
+{
+    s0 = D.b.start[cidx(D.g, x0, y, z)];
+    return D.b.start[cidx(D.g, x1 - 1, y, z) + 1] - s0;
+}
+
+// particles per block row, scanned within blocks of kScanPerBlock rows
+__global__ __launch_bounds__(kBlock) void k_order_scan(Desc D)
+{
+    __shared__ int wsum[kBlock / 64];
+    const int64_t n = D.o.nrows;
+    const int64_t base = (int64_t)blockIdx.x * kScanPerBlock + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int tot = 0;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        int x0, x1, y, z, s0;
+        v[t] = (base + t < n && order_row(D, base + t, x0, x1, y, z)) ? order_row_count(D, x0, x1, y, z, s0) : 0;
+        tot += v[t];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int incl = tot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    int run = incl - tot, btot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+        const int ws = wsum[w];
+        if (w < wv) run += ws;
+        btot += ws;
+    }
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        if (base + t < n) D.o.rowoff[base + t] = run;
+        run += v[t];
+    }
+    if (threadIdx.x == kBlock - 1) D.o.rowsum[blockIdx.x] = btot;
+}
+
+// porder[offset of row r + k] = first slot of row r + k
+__global__ __launch_bounds__(kBlock) void k_order_fill(Desc D)
+{
+    const int64_t r = gidx();
+    if (r >= D.o.nrows || halted(D)) return;
+    int x0, x1, y, z, s0;
+    if (!order_row(D, r, x0, x1, y, z)) return;
+    const int cnt = order_row_count(D, x0, x1, y, z, s0);
+    const int off = D.o.rowoff[r] + D.o.rowsum[r / kScanPerBlock];
+    for (int k = 0; k < cnt; ++k) D.o.porder[off + k] = s0 + k;
 }
 
 // semi-implicit Euler with the fluid forces frozen (Sec. 3.3); periodic wrap;
@@ -1470,7 +1555,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(Desc D)
 {
     const int64_t i = gidx();
     const Parts &P = D.pt;
-    if (i >= P.np) return;
+    if (i >= P.np || halted(D)) return;
     const int64_t cap = P.cap;
     atomicAdd(&D.b.cnt[particle_cell(D.g, P.x[i], P.x[cap + i], P.x[2 * cap + i])], 1);
 }
@@ -1574,7 +1659,7 @@ __global__ __launch_bounds__(kBlock) void k_place(Desc D)
 {
     const int64_t i = gidx();
     const Parts &P = D.pt;
-    if (i >= P.np) return;
+    if (i >= P.np || halted(D)) return;
     const int64_t cap = P.cap;
     const int64_t c = particle_cell(D.g, P.x[i], P.x[cap + i], P.x[2 * cap + i]);
     const int pos = bin_start(D.b, c) + atomicAdd(&D.b.cnt[c], 1);
@@ -1587,7 +1672,7 @@ __global__ __launch_bounds__(kBlock) void k_cellsort(Desc D)
 {
     const int64_t nc = D.g.nc;
     const int64_t c = gidx();
-    if (c >= nc) return;
+    if (c >= nc || halted(D)) return;
     D.b.cnt[c] = 0;
     const int p0 = bin_start(D.b, c), p1 = c + 1 < nc ? bin_start(D.b, c + 1) : D.b.start[nc];
     D.b.start[c] = p0;
@@ -1659,7 +1744,7 @@ __device__ __forceinline__ void permute_slot(const Desc &D, int64_t s, double x[
 __global__ __launch_bounds__(kBlock) void k_permute(Desc D)
 {
     const int64_t s = gidx();
-    if (s >= D.pt.np) return;
+    if (s >= D.pt.np || halted(D)) return;
     double x[3], u[3], a[3], d;
     Stencil st;
     permute_slot(D, s, x, u, a, d, st);
@@ -1673,7 +1758,7 @@ template <typename R>
 __global__ __launch_bounds__(kBlock) void k_permute_am(Desc D, Cells<R> C)
 {
     const int64_t s = gidx();
-    if (s >= D.pt.np) return;
+    if (s >= D.pt.np || halted(D)) return;
     double x[3], u[3], a[3], d;
     Stencil st;
     permute_slot(D, s, x, u, a, d, st);
@@ -2135,6 +2220,14 @@ void launch_dem_force(const Desc &D, hipStream_t s)
     if (D.pt.np == 0) return;
     if (D.pt.pk) hipLaunchKernelGGL((k_dem_force<double, true>), dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
     else hipLaunchKernelGGL((k_dem_force<double, false>), dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+}
+void launch_dem_order(const Desc &D, hipStream_t s)
+{
+    if (D.pt.np == 0 || !D.t.dem_order) return;
+    const unsigned nb = nblocks(D.o.nrows, kScanPerBlock);
+    hipLaunchKernelGGL(k_order_scan, dim3(nb), dim3(kBlock), 0, s, D);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, D.o.rowsum, (int)nb, D.o.rowsum + nb);
+    hipLaunchKernelGGL(k_order_fill, dim3(nblocks(D.o.nrows)), dim3(kBlock), 0, s, D);
 }
 void launch_nlist(const Desc &D, hipStream_t s)
 {

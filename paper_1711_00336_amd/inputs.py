@@ -400,10 +400,19 @@ def case_dilute_periodic(seed=0, n=128, eps_p=0.05, d=0.8, precision="fp32dev"):
     return Case(f"periodic-{n}^3-eps{eps_p}", p, parts, seed)
 
 
+# The dense suspension runs at tau = 0.51 (the workload does not state a
+# relaxation time). At tau = 0.7 the explicit two-way drag coupling of a
+# solid fraction of 0.4 diverges in the FP64 oracle itself within ~20 steps,
+# with or without lubrication and added mass: against the particles' drag
+# the fluid relaxes faster than one LBM step. Near tau = 1/2, the regime of
+# the paper's water runs, it stays stable.
+DENSE_TAU = 0.51
+
+
 def dense_walled_params(n=(256, 256, 512), precision="fp32dev", n_dem=10, n_int=10):
-    """Parameters of the dense suspension: walls in z, tau = 0.7, gravity
-    1e-5 on the particles, restitution 0.9, lubrication cut-off 1.0."""
-    return Params(n=tuple(n), periodic=(1, 1, 0), tau=0.7, gravity=(0.0, 0.0, -1e-5),
+    """Parameters of the dense suspension: walls in z, tau = DENSE_TAU,
+    gravity 1e-5 on the particles, restitution 0.9, lubrication cut-off 1.0."""
+    return Params(n=tuple(n), periodic=(1, 1, 0), tau=DENSE_TAU, gravity=(0.0, 0.0, -1e-5),
                   body_force_auto=0, e_n=0.9, mu_c=0.25, T_c=0.0, h_c=1.0,
                   n_int=n_int, n_dem=n_dem, precision=precision)
 

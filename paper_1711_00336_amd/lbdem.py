@@ -60,6 +60,10 @@ class lbdem_state_view(C.Structure):
                 ("rho_p", C.c_void_p)]
 
 
+class lbdem_tuning(C.Structure):
+    _fields_ = [("gather_variant", C.c_int32), ("dem_order", C.c_int32), ("dem_block", C.c_int32 * 3)]
+
+
 class lbdem_request(C.Structure):
     _fields_ = [("params", lbdem_params), ("np", C.c_int64), ("x", C.c_void_p), ("u", C.c_void_p),
                 ("omega", C.c_void_p), ("d", C.c_void_p), ("rho_p", C.c_void_p),
@@ -115,6 +119,8 @@ def lib():
             "lbdem_set_timing": (st, [H, C.c_int]),
             "lbdem_autotune": (st, [H, C.POINTER(C.c_int32)]),
             "lbdem_set_gather_variant": (st, [H, C.c_int32]),
+            "lbdem_get_tuning": (st, [H, C.POINTER(lbdem_tuning)]),
+            "lbdem_set_tuning": (st, [H, C.POINTER(lbdem_tuning)]),
             "lbdem_batch_create": (st, [C.c_int32, C.POINTER(lbdem_params), C.c_void_p, C.POINTER(H)]),
             "lbdem_batch_domain": (st, [H, C.c_int32, C.POINTER(H)]),
             "lbdem_batch_size": (C.c_int32, [H]),
@@ -316,6 +322,15 @@ class Domain:
 
     def lbdem_set_timing(self, on: bool):
         _check(self.h, lib().lbdem_set_timing(self.h, 1 if on else 0))
+
+    def lbdem_get_tuning(self):
+        T = lbdem_tuning()
+        _check(self.h, lib().lbdem_get_tuning(self.h, C.byref(T)))
+        return dict(gather_variant=T.gather_variant, dem_order=T.dem_order, dem_block=tuple(T.dem_block[:]))
+
+    def lbdem_set_tuning(self, gather_variant=-1, dem_order=-1, dem_block=(32, 32, 32)):
+        T = lbdem_tuning(int(gather_variant), int(dem_order), (C.c_int32 * 3)(*[int(v) for v in dem_block]))
+        _check(self.h, lib().lbdem_set_tuning(self.h, C.byref(T)))
 
     def lbdem_autotune(self):
         v = C.c_int32(-1)
