@@ -96,7 +96,7 @@ def workload(name, seed, cache=None):
     raise SystemExit(f"unknown workload {name}")
 
 
-def mean_list_length(case, vskin=0.25, max_query=100000):
+def mean_list_length(case, vskin=0.1, max_query=100000):
     """Mean Verlet-list length of the initial packing: neighbours within
     (d_i + d_j)/2 + h_c + skin (the list reach of the DEM kernels), over all
     particles or an evenly spaced sample of max_query of them."""

@@ -301,9 +301,12 @@ void resolve_phys(lbdem_domain_t h)
     // a particle may move at most `skin` within one subcycle (else the step
     // is flagged unstable); Verlet lists carry `vskin` beyond the interaction
     // reach and are rebuilt once a particle has moved vskin/2 - skin since
-    // the build, so every pair within reach stays listed
-    P.skin = 0.1;
-    P.vskin = 0.25;
+    // the build, so every pair within reach stays listed. A fifth of a
+    // tenth of a cell per subcycle is far above the settling speeds of these
+    // workloads (1e-4 cells per step at most), and a thin skin keeps the
+    // lists close to the pairs within reach.
+    P.skin = 0.02;
+    P.vskin = 0.1;
     P.rbin = 1;
 }
 

@@ -1114,6 +1114,20 @@ template <typename T> __device__ __forceinline__ T dot3(const T a[3], const T b[
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// 1/x in FP64 from the hardware reciprocal estimate refined by two Newton
+// steps (error below one ulp of the correctly rounded quotient for the
+// positive, normal arguments used here): a third of the instructions of a
+// full IEEE division
+__device__ __forceinline__ double rcp64(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp64(float x) { return 1.0f / x; }
+
 // spring-dashpot normal force and Coulomb-limited tangential force; torque
 // about the centre is (d_i/2) n x F^t (the moment of F^t at the contact point)
 template <typename T>
@@ -1134,9 +1148,9 @@ __device__ __forceinline__ void contact(const Phys &p, T delta, const T n[3], co
     T Ft[3] = {(T)0, (T)0, (T)0};
     if (urt_n > (T)0) {
         const T fn_n = sqrt(dot3(Fn, Fn));
-        const T mag = fmin((T)p.mu_c * fn_n, xi * urt_n);
+        const T mag = fmin((T)p.mu_c * fn_n, xi * urt_n) * rcp64(urt_n);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) Ft[a] = -mag * urt[a] / urt_n;
+        for (int a = 0; a < 3; ++a) Ft[a] = -mag * urt[a];
     }
     T tq[3];
     cross3(n, Ft, tq);
@@ -1148,35 +1162,37 @@ __device__ __forceinline__ void contact(const Phys &p, T delta, const T n[3], co
 }
 
 // Eq. lubrication_force, applied for h < h_c with h := max(h, h_min) and,
-// when lub_stab is set, h >= 3 pi mu <d>^2 dt_DEM / (8 m_ij)
+// when lub_stab is set, h >= 3 pi mu <d>^2 dt_DEM / (8 m_ij); inv_dm = 1/<d>
 template <typename T>
-__device__ __forceinline__ void lubrication(const Phys &p, T h, T dm, T mij, const T n[3], const T upr[3], T F[3])
+__device__ __forceinline__ void lubrication(const Phys &p, T h, T dm, T inv_dm, T mij, const T n[3], const T upr[3],
+                                            T F[3])
 {
     if (!(h < (T)p.h_c)) return;
     const T mu = (T)p.mu;
     const T pi = (T)M_PI;
     T he = fmax(h, (T)p.h_min);
-    if (p.lub_stab) he = fmax(he, (T)3 * pi * mu * dm * dm * (T)p.dt_dem / ((T)8 * mij));
-    const T Lg = log(dm / ((T)2 * he));
-    const T asq = (T)1.5 * pi * mu * dm * (dm / ((T)4 * he) + ((T)18 / (T)40) * Lg + ((T)9 / (T)84) * (he / dm) * Lg);
+    if (p.lub_stab) he = fmax(he, (T)3 * pi * mu * dm * dm * (T)p.dt_dem * rcp64((T)8 * mij));
+    const T inv_he = rcp64(he);
+    const T Lg = log(dm * (T)0.5 * inv_he);
+    const T asq = (T)1.5 * pi * mu * dm * (dm * (T)0.25 * inv_he + ((T)18 / (T)40) * Lg + ((T)9 / (T)84) * (he * inv_dm) * Lg);
     const T ash = (T)0.5 * pi * mu * dm * Lg * (dm + he) * (dm + he) / (T)4;
     const T un = dot3(upr, n);
-    const T s = (T)2 / (he + dm);
+    const T s = (T)2 * rcp64(he + dm);
 #pragma unroll
     for (int a = 0; a < 3; ++a) F[a] += -asq * un * n[a] - ash * s * s * (upr[a] - un * n[a]);
 }
 
+// contact and lubrication of the pair (i, j) at centre offset dx = x_j - x_i,
+// |dx|^2 = dist2 below the interaction reach
 template <typename T>
 __device__ __forceinline__ void pair_interaction(const Phys &p, const PV<T> &pi, const PV<T> &pj, const double dx[3],
-                                                 T F[3], T Tq[3])
+                                                 double dist2, T F[3], T Tq[3])
 {
-    const double dist2 = dot3(dx, dx);
-    const double reach = pi.rr + pj.rr + (p.use_lub ? fmax(p.h_c, 0.0) : 0.0);
-    if (dist2 >= reach * reach) return;
     const double dist = sqrt(dist2);
-    const T n[3] = {(T)(dx[0] / dist), (T)(dx[1] / dist), (T)(dx[2] / dist)};
+    const double inv = rcp64(dist);
+    const T n[3] = {(T)(dx[0] * inv), (T)(dx[1] * inv), (T)(dx[2] * inv)};
     const T delta = (T)(pi.rr + pj.rr - dist);
-    const T mij = pi.m * pj.m / (pi.m + pj.m);
+    const T mij = pi.m * pj.m * rcp64(pi.m + pj.m);
     if (delta > (T)0) {
         T s[3], ur[3];
 #pragma unroll
@@ -1187,9 +1203,11 @@ __device__ __forceinline__ void pair_interaction(const Phys &p, const PV<T> &pi,
         contact(p, delta, n, ur, mij, pi.r, F, Tq);
     }
     if (p.use_lub) {
-        const T dm = (T)2 * pi.d * pj.d / (pi.d + pj.d);
+        const T sd = pi.d + pj.d, pd = pi.d * pj.d;
+        const T dm = (T)2 * pd * rcp64(sd);
+        const T inv_dm = (T)0.5 * sd * rcp64(pd);
         const T upr[3] = {pi.u[0] - pj.u[0], pi.u[1] - pj.u[1], pi.u[2] - pj.u[2]};
-        lubrication(p, -delta, dm, mij, n, upr, F);
+        lubrication(p, -delta, dm, inv_dm, mij, n, upr, F);
     }
 }
 
@@ -1212,7 +1230,7 @@ __device__ __forceinline__ void wall_interaction(const Phys &p, const Geo &g, co
                 for (int b = 0; b < 3; ++b) ur[b] += pi.u[b];
                 contact(p, delta, n, ur, pi.m, pi.r, F, Tq);
             }
-            if (p.use_lub) lubrication(p, -delta, (T)2 * pi.d, pi.m, n, pi.u, F);
+            if (p.use_lub) lubrication(p, -delta, (T)2 * pi.d, (T)0.5 * rcp64(pi.d), pi.m, n, pi.u, F);
         }
     }
 }
@@ -1403,8 +1421,9 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
             double dx[3] = {pj[c].x[0] - pi.x[0], pj[c].x[1] - pi.x[1], pj[c].x[2] - pi.x[2]};
             min_image(D.g, dx);
             const double reach = pi.rr + pj[c].rr + gap;
-            if (dot3(dx, dx) >= reach * reach) continue;
-            pair_interaction(D.p, pi, pj[c], dx, F, Tq);
+            const double dist2 = dot3(dx, dx);
+            if (dist2 >= reach * reach) continue;
+            pair_interaction(D.p, pi, pj[c], dx, dist2, F, Tq);
         }
     }
     wall_interaction(D.p, D.g, pi, F, Tq);
