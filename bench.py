@@ -1,10 +1,12 @@
 #!/usr/bin/env python3
 """Throughput of the coupled LBM-DEM time step on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dilute|dilute64|small|dense]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload dense|dilute|dilute64|small]
     python bench.py --mode batch [--domains 256] [--steps K]
     python bench.py --mode serve [--requests R] [--rates 10,100]
     python bench.py --mode k10      (stream-collide alone on 256x256x512)
+    python bench.py --mode bounce [--stokes 8,20,128]   (sphere-wall collision, Sec. 5)
+    python bench.py --mode settle [--fractions 0,0.1,0.3]  (hindered settling vs Richardson-Zaki, Sec. 4)
 
 A step is one full coupled time step (Alg. 1 of the paper): moments, Du_f/Dt
 and grad P, n_int interaction subcycles (added mass, drag, pressure and
@@ -21,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -529,6 +532,144 @@ def run_step_workload(lbdem, torch, case, wl_name, K, W, ksteps, stream, args):
                 nlist=nlist, nreach=nreach, tuning=dict(tuning, dem_order_resolved=dem_order))
 
 
+def richardson_zaki(eps, re_t):
+    """<u_pS>/u_pT = (1 - <eps_p>)^kappa with Richardson and Zaki's kappa(Re_T)
+    (Sec. 4, Eqs. hinderedSettlingCorrelation, hinderedCoefficientRZ)."""
+    if re_t < 0.2:
+        k = 4.65
+    elif re_t < 1.0:
+        k = 4.35 * re_t ** -0.03
+    elif re_t < 500.0:
+        k = 4.45 * re_t ** -0.1
+    else:
+        k = 2.39
+    return (1.0 - eps) ** k
+
+
+def bench_settle(args):
+    """Hindered settling (Sec. 4) against Richardson-Zaki: a fully periodic
+    cube of 32 diameters (d = 0.5 cell, 16^3 cells), spheres at solid
+    fractions from one sphere to 0.5, the paper's glass-in-water parameters
+    mapped to tau = 0.505 with the Smagorinsky model (inputs.
+    case_hindered_settling), 30 t_St coupled steps (t_St = rho_p d^2 / 18 mu);
+    <u_pS> averaged over the last 10 t_St. u_pT is the single sphere's
+    settling velocity in the same box, Re_T = u_pT d / nu."""
+    import torch
+    from paper_1711_00336_amd import inputs as I
+    from paper_1711_00336_amd import lbdem
+    torch.cuda.init()
+    fracs = [float(x) for x in args.fractions.split(",")]
+    pts = []
+    for eps in fracs:
+        case = I.case_hindered_settling(args.seed, eps, precision=args.settle_precision)
+        mu = (case.params.tau - 0.5) / 3.0
+        t_st = 2.5 * 0.25 / (18.0 * mu)
+        nsteps, navg = int(round(30 * t_st)), int(round(10 * t_st))
+        t0 = time.perf_counter()
+        status, ups = "ok", []
+        try:
+            with lbdem.Domain(case.params) as dom:
+                dom.add(case.particles)
+                dom.step(nsteps - navg)
+                for _ in range(navg):
+                    dom.step(1)
+                    ups.append(dom.lbdem_diagnostics()["u_ps"])
+        except lbdem.LbdemError as e:
+            status = f"status {e.status}: {e}"
+        pts.append({"eps_p": eps, "particles": int(case.particles.n), "steps": nsteps, "status": status,
+                    "u_ps": float(np.mean(ups)) if ups and status == "ok" else None,
+                    "seconds": round(time.perf_counter() - t0, 2)})
+        print(f"[bench] settle eps {eps}: {case.particles.n} spheres, <u_pS> {pts[-1]['u_ps']} ({status}, "
+              f"{pts[-1]['seconds']} s)", file=sys.stderr, flush=True)
+    single = next((p for p in pts if p["eps_p"] == 0.0 and p["u_ps"] is not None), None)
+    if single:
+        u_t = abs(single["u_ps"])
+        re_t = u_t * 0.5 / ((0.505 - 0.5) / 3.0)
+        for p in pts:
+            if p["u_ps"] is not None:
+                p["ratio"] = round(abs(p["u_ps"]) / u_t, 4)
+                p["richardson_zaki"] = round(richardson_zaki(p["eps_p"], re_t), 4)
+    out = {"metric": METRIC, "mode": "settle", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "hindered-settling-16^3-d0.5", "tau": 0.505, "les": True, "n_int": 10,
+                      "n_dem": 50, "precision": args.settle_precision,
+                      "u_pT": single["u_ps"] if single else None,
+                      "Re_T": round(re_t, 3) if single else None},
+           "points": pts,
+           "context": "paper Table 2 A0: <u_pS>/u_pT = 0.288 at <eps_p> = 0.3 (Re_T = 16.8); "
+                      "Richardson-Zaki 0.302 there"}
+    print(json.dumps(out), flush=True)
+    return out
+
+
+def bench_bounce(args):
+    """Sphere-wall collision (Sec. 5): e_wet/e_n against the Stokes number.
+    A sphere (d = 0.5 cell, tau = 0.51) is launched downwards at about its
+    Stokes terminal speed in a closed 16 x 16 x 64 column (32 d x 32 d x
+    128 d; the paper drops it from rest in a 512 d column) and tracked every
+    step. The approach speed u_A is the speed while the gap still exceeds the
+    lubrication cut-off h_c = d; the impact t_I is the first sample moving
+    upwards after the sphere reached the wall; the rebound speed u_R is taken
+    t_R = 0.1 d/u_A later (at least one step), as in Sec. 5.2;
+    e_wet/e_n = u_R / (u_A e_n), St = (rho_p/rho_f) u_A d / (9 mu). The
+    density ratio sets the Stokes number at a stable tau. Both readings of
+    the lubrication force while the sphere overlaps the wall are run."""
+    import torch
+    from paper_1711_00336_amd import inputs as I
+    from paper_1711_00336_amd import lbdem
+    torch.cuda.init()
+    d, tau, uT = 0.5, 0.51, 0.03
+    mu = (tau - 0.5) / 3.0
+    sts = [float(x) for x in args.stokes.split(",")]
+    lines = []
+    for lub_contact in (0, 1):
+        pts = []
+        for st in sts:
+            rho = 9.0 * mu * st / (uT * d)
+            g = 18.0 * mu * uT / ((rho - 1.0) * d * d)   # Stokes' law for the launch speed
+            case = I.case_sphere_wall(d=d, rho_ratio=rho, g=g, tau=tau, n=(16, 16, 64), z0=64 - 2 * d, u0=uT,
+                                      lub_contact=lub_contact)
+            t0 = time.perf_counter()
+            with lbdem.Domain(case.params) as dom:
+                dom.add(case.particles)
+                uA = None
+                hit = False
+                tI = None
+                uR = None
+                k = 0
+                while k < 6000:
+                    dom.step(1)
+                    k += 1
+                    x, u, _, _ = dom.lbdem_read_particles()
+                    gap, uz = x[0, 2] - 0.5 * d, u[0, 2]
+                    if gap > d:
+                        uA = uz
+                    if gap < 0.02:
+                        hit = True
+                    if hit and tI is None and uz > 0.0:
+                        tI = k
+                    if tI is not None and uA is not None and k >= tI + max(1, math.ceil(0.1 * d / abs(uA))):
+                        uR = uz
+                        break
+                    if hit and tI is None and k > 200 + 2 * 64 / uT:
+                        break
+            e = (uR / (-uA) / 0.97) if (uR is not None and uA) else 0.0
+            pts.append({"St": round(rho * abs(uA) * d / (9.0 * mu), 2) if uA else None, "rho_ratio": round(rho, 2),
+                        "g": g, "u_approach": uA, "u_rebound": uR, "e_wet_over_e_n": round(e, 4),
+                        "steps": k, "seconds": round(time.perf_counter() - t0, 2)})
+            print(f"[bench] bounce lub_contact={lub_contact} St {pts[-1]['St']}: e_wet/e_n {e:.3f} "
+                  f"({k} steps, {pts[-1]['seconds']} s)", file=sys.stderr, flush=True)
+        line = {"metric": METRIC, "mode": "bounce", "n_gpus": 1, "data": "synthetic",
+                "config": {"workload": "sphere-wall-16x16x64-d0.5", "tau": tau, "n_int": 10, "n_dem": 50,
+                           "T_c": d, "e_n": 0.97, "mu_c": 0.1, "h_c": d, "precision": "fp64",
+                           "lubrication_in_contact": bool(lub_contact)},
+                "points": pts,
+                "context": "paper Table 3 baseline B0: e_wet/e_n = 0.792 at St = 128 (d/dx = 1/2, other "
+                           "lattice parameters); no rebound below St ~ 17; e_wet -> e_n above St ~ 600"}
+        print(json.dumps(line), flush=True)
+        lines.append(line)
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -541,7 +682,12 @@ def main():
     ap.add_argument("--no-dilute", action="store_true", help="skip the 128^3 dilute run beside the dense one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--mode", choices=("step", "batch", "serve", "k10"), default="step")
+    ap.add_argument("--mode", choices=("step", "batch", "serve", "k10", "bounce", "settle"), default="step")
+    ap.add_argument("--fractions", default="0,0.05,0.1,0.2,0.3,0.4,0.5",
+                    help="settle mode: solid fractions (0: a single sphere)")
+    ap.add_argument("--settle-precision", default="fp64", choices=("fp64", "fp32dev"))
+    ap.add_argument("--stokes", default="8,20,40,80,128,250,500",
+                    help="bounce mode: target Stokes numbers")
     ap.add_argument("--domains", type=int, default=256)
     ap.add_argument("--requests", type=int, default=16)
     ap.add_argument("--rates", default="10,1000")
@@ -557,9 +703,9 @@ def main():
     args = ap.parse_args()
     dense = args.mode == "step" and args.workload == "dense"
     if args.steps is None:
-        args.steps = 20 if dense else {"step": 200, "batch": 20, "serve": 0, "k10": 0}[args.mode]
+        args.steps = 20 if dense else {"step": 200, "batch": 20}.get(args.mode, 0)
     if args.warmup is None:
-        args.warmup = 5 if dense else {"step": 20, "batch": 3, "serve": 0, "k10": 0}[args.mode]
+        args.warmup = 5 if dense else {"step": 20, "batch": 3}.get(args.mode, 0)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this library runs on one GPU only; --gpus must be 1 "
               "(the spatial decomposition across GPUs is designed, not implemented)", file=sys.stderr)
@@ -568,6 +714,10 @@ def main():
         return bench_batch(args)
     if args.mode == "serve":
         return bench_serve(args)
+    if args.mode == "bounce":
+        return bench_bounce(args)
+    if args.mode == "settle":
+        return bench_settle(args)
     if args.mode == "k10":
         import torch
         from paper_1711_00336_amd import lbdem

@@ -106,6 +106,13 @@ typedef struct lbdem_params {
                                 With either flag, tau_e replaces tau in the
                                 collision and in the forcing prefactor; tau
                                 stays the pure-fluid value of the closures. */
+    int32_t lub_contact;     /* 1 (default): lubrication (Eq. lubrication_force) also
+                                while two spheres or a sphere and a wall overlap,
+                                with the gap clamped at h_min as the text of
+                                Sec. 3.1.3 reads; 0: on the open gap only (h > 0),
+                                the reading that reproduces the rebound of Sec. 5
+                                (Table 3), where the clamped force overdamps the
+                                contact at the Stokes numbers studied. */
 } lbdem_params;
 
 /* lbdem_params.flags: launch every kernel of a step directly instead of
@@ -141,7 +148,8 @@ const char *lbdem_last_error(lbdem_domain_t h);
 
 /* Paper defaults: rho_f=1, e_n=0.88, mu_c=0.25 (Sec. 4.1), h_min=1e-5
  * (Sec. 3.1.3), c_am=0.5 (Table 1), n_int=10 (Sec. 4.1), n_dem=1, T_c auto,
- * h_c=0.5, lubrication and added mass on, FP64, 32x32x32 periodic, tau=0.8. */
+ * h_c=0.5, lubrication (also in contact) and added mass on, FP64, 32x32x32
+ * periodic, tau=0.8. */
 lbdem_status lbdem_params_default(lbdem_params *p);
 
 /* Route device allocations through a caller allocator (e.g. a framework's

@@ -87,6 +87,7 @@ typedef struct {
     double c_am;
     int32_t use_lift;  /* shear-induced lift (Table 1) on/off */
     int32_t use_eilers, use_les;  /* per-cell tau_e: Eilers viscosity, Smagorinsky LES */
+    int32_t lub_contact;  /* 1: lubrication also while spheres overlap (gap clamped); 0: open gap only */
 } orc_params;
 
 typedef struct {
@@ -565,11 +566,17 @@ static void contact(const orc_params *p, double delta, const double n[3], const 
  * Reading (explicit stability): the gap is also floored at
  * h_stab = 3 pi mu dm^2 dt_DEM / (8 m_ij), where the leading term of a_sq
  * makes a_sq dt_DEM / m_ij = 1; below it the explicit update of the squeeze
- * force would overshoot. It only acts when lub_stab is set. */
+ * force would overshoot. It only acts when lub_stab is set.
+ * Reading for overlapping spheres (h <= 0): the text clamps the gap at
+ * h_min and applies the force (lub_contact = 1, the default); the collision
+ * results of Sec. 5 (a rebound near e_n at large Stokes numbers, Table 3)
+ * need the force on the open gap only (lub_contact = 0), as the clamped
+ * force overdamps the contact spring at those Stokes numbers. */
 static void lubrication(const orc_params *p, double h, double dm, double mij, const double n[3],
                         const double upr[3], double dt_dem, double F[3])
 {
     if (!(h < p->h_c)) return;
+    if (!p->lub_contact && !(h > 0.0)) return;
     double mu = mu0(p);
     double he = fmax(h, p->h_min);
     if (p->lub_stab) he = fmax(he, 3.0 * M_PI * mu * dm * dm * dt_dem / (8.0 * mij));

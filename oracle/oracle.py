@@ -41,7 +41,7 @@ class Params(C.Structure):
                 ("lub_stab", C.c_int32), ("use_lub", C.c_int32), ("use_am", C.c_int32),
                 ("n_int", C.c_int32), ("n_dem", C.c_int32),
                 ("c_am", C.c_double), ("use_lift", C.c_int32),
-                ("use_eilers", C.c_int32), ("use_les", C.c_int32)]
+                ("use_eilers", C.c_int32), ("use_les", C.c_int32), ("lub_contact", C.c_int32)]
 
 
 class State(C.Structure):
@@ -166,6 +166,7 @@ def make_params(prm) -> Params:
     P.use_lift = int(getattr(prm, "use_lift", 0))
     P.use_eilers = int(getattr(prm, "use_eilers", 0))
     P.use_les = int(getattr(prm, "use_les", 0))
+    P.lub_contact = int(getattr(prm, "lub_contact", 1))
     return P
 
 

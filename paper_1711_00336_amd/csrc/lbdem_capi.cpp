@@ -287,6 +287,7 @@ void resolve_phys(lbdem_domain_t h)
     P.use_lift = p.use_lift ? 1 : 0;
     P.use_eilers = p.use_eilers ? 1 : 0;
     P.use_les = p.use_les ? 1 : 0;
+    P.lub_contact = p.lub_contact ? 1 : 0;
     P.n_int = p.n_int;
     P.n_dem = p.n_dem;
     P.dt_int = 1.0 / p.n_int;
@@ -816,6 +817,7 @@ lbdem_status lbdem_params_default(lbdem_params *p)
     p->n_dem = 1;
     p->c_am = 0.5;
     p->precision = LBDEM_FP64;
+    p->lub_contact = 1;
     return LBDEM_OK;
 }
 

@@ -24,6 +24,7 @@ struct Phys {
     double g[3], fb[3];         // particle gravity, fluid body-force density
     double e_n, mu_c, T_c, h_c, h_min;
     int lub_stab, use_lub, use_am;
+    int lub_contact;            // lubrication also while the spheres overlap (gap clamped)
     int use_lift;               // shear-induced lift with the lattice curl
     int use_eilers, use_les;    // per-cell tau_e: Eilers viscosity, Smagorinsky LES
     int n_int, n_dem;

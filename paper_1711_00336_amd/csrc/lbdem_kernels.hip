@@ -1162,12 +1162,14 @@ __device__ __forceinline__ void contact(const Phys &p, T delta, const T n[3], co
 }
 
 // Eq. lubrication_force, applied for h < h_c with h := max(h, h_min) and,
-// when lub_stab is set, h >= 3 pi mu <d>^2 dt_DEM / (8 m_ij); inv_dm = 1/<d>
+// when lub_stab is set, h >= 3 pi mu <d>^2 dt_DEM / (8 m_ij); inv_dm = 1/<d>.
+// With lub_contact = 0 only on the open gap (h > 0).
 template <typename T>
 __device__ __forceinline__ void lubrication(const Phys &p, T h, T dm, T inv_dm, T mij, const T n[3], const T upr[3],
                                             T F[3])
 {
     if (!(h < (T)p.h_c)) return;
+    if (!p.lub_contact && !(h > (T)0)) return;  // open gap only
     const T mu = (T)p.mu;
     const T pi = (T)M_PI;
     T he = fmax(h, (T)p.h_min);

@@ -90,6 +90,7 @@ class Params:
     use_lift: int = 0                       # shear-induced lift (Table 1)
     use_eilers: int = 0                     # Eilers viscosity of the suspension in tau_e
     use_les: int = 0                        # Smagorinsky subgrid viscosity in tau_e
+    lub_contact: int = 1                    # lubrication also while spheres overlap (0: open gap only)
     precision: str = "fp64"                 # "fp64" | "fp32dev"
     flags: int = 0                          # library flags (1: no graph replay)
 
@@ -424,6 +425,55 @@ def case_dense_walled(seed=0, n=(256, 256, 512), eps_p=0.4, precision="fp32dev",
     p = dense_walled_params(n, precision, n_dem, n_int)
     parts = make_particles(seed, p, float(eps_p), 0.9, 1.1, 2.5, progress=progress)
     return Case(f"dense-{n[0]}x{n[1]}x{n[2]}-eps{eps_p}", p, parts, seed)
+
+
+def case_sphere_wall(d=0.5, rho_ratio=192.0, g=1e-4, tau=0.51, n=None, z0=None, u0=0.0, n_int=10, n_dem=None,
+                     h_c=None, use_am=1, use_lub=1, lub_contact=1, precision="fp64"):
+    """One sphere dropped towards the bottom wall of a closed box (Sec. 5.1
+    Setup): box 32 d x 32 d x 512 d (n overrides, in cells), no-slip walls on
+    every side, the sphere horizontally centred at height z0 (default 4 d
+    below the lid) with downward velocity u0, gravity g on the sphere only,
+    dry restitution 0.97, friction 0.1, collision time d (in LBM steps per
+    cell, T_c = d_p/dx dt), n_int = 10 and n_DEM = 25 dx/d_p substeps,
+    lubrication cut-off h_c = d. The paper reaches its Stokes numbers with
+    low viscosities; here tau stays at a stable value and the density ratio
+    sets the Stokes number."""
+    if n is None:
+        n = (int(round(32 * d)), int(round(32 * d)), int(round(512 * d)))
+    if z0 is None:
+        z0 = n[2] - 4.0 * d
+    if n_dem is None:
+        n_dem = max(1, int(round(25.0 / d)))
+    p = Params(n=tuple(n), periodic=(0, 0, 0), tau=tau, gravity=(0.0, 0.0, -abs(g)), body_force_auto=0,
+               e_n=0.97, mu_c=0.1, T_c=d, h_c=d if h_c is None else h_c, n_int=n_int, n_dem=n_dem,
+               use_am=use_am, use_lub=use_lub, lub_contact=lub_contact, precision=precision)
+    x = np.array([[0.5 * n[0], 0.5 * n[1], float(z0)]])
+    u = np.array([[0.0, 0.0, -abs(u0)]])
+    parts = Particles(x, u, np.zeros((1, 3)), np.array([float(d)]), np.array([float(rho_ratio)]))
+    return Case(f"sphere-wall-{n[0]}x{n[1]}x{n[2]}-d{d}-rho{rho_ratio:g}", p, parts, 0)
+
+
+def case_hindered_settling(seed, eps_p, d=0.5, tau=0.505, g=9.35e-3, edge_d=32, use_les=1, precision="fp64",
+                           n_int=10, n_dem=50):
+    """Hindered settling (Sec. 4.1 Setup): a fully periodic cube of edge_d
+    diameters, uniform spheres at solid fraction eps_p (eps_p = 0: a single
+    sphere) at rest, density ratio 2.5, restitution 0.88, friction 0.25,
+    T_c = dt/2, h_c = d, n_int = 10, n_DEM = 50, gravity g on the spheres and
+    the balancing fluid body force. The defaults map the paper's glass
+    spheres in water (d = 0.35 mm = d cells, nu = 1e-6 m^2/s, g = 9.81 m/s^2)
+    to lattice units at tau = 0.505: dx = 0.7 mm, dt = nu_lat dx^2/nu =
+    0.817 ms, g dt^2/dx = 9.35e-3, with the Smagorinsky model on as in the
+    paper's baseline."""
+    n = int(round(edge_d * d))
+    p = Params(n=(n, n, n), periodic=(1, 1, 1), tau=tau, gravity=(0.0, 0.0, -abs(g)), body_force_auto=1,
+               e_n=0.88, mu_c=0.25, T_c=0.5, h_c=d, n_int=n_int, n_dem=n_dem, use_les=use_les, precision=precision)
+    if eps_p <= 0.0:
+        c = 0.5 * n
+        parts = Particles(np.array([[c + 0.13, c - 0.07, c + 0.21]]), np.zeros((1, 3)), np.zeros((1, 3)),
+                          np.array([float(d)]), np.array([2.5]))
+    else:
+        parts = make_particles(seed, p, count_for_fraction(eps_p, n ** 3, d), d, d, 2.5)
+    return Case(f"hindered-{n}^3-eps{eps_p:.2f}", p, parts, seed)
 
 
 def batch_domain_draw(seed, i, edge_lo=16, edge_hi=96):

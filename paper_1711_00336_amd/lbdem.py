@@ -43,7 +43,8 @@ class lbdem_params(C.Structure):
                 ("lub_stab", C.c_int32), ("use_lub", C.c_int32), ("use_am", C.c_int32),
                 ("n_int", C.c_int32), ("n_dem", C.c_int32),
                 ("c_am", C.c_double), ("precision", C.c_int32), ("flags", C.c_uint32),
-                ("use_lift", C.c_int32), ("use_eilers", C.c_int32), ("use_les", C.c_int32)]
+                ("use_lift", C.c_int32), ("use_eilers", C.c_int32), ("use_les", C.c_int32),
+                ("lub_contact", C.c_int32)]
 
 
 class lbdem_diag(C.Structure):
@@ -176,6 +177,7 @@ def params_from(prm) -> lbdem_params:
     P.use_lift = int(getattr(prm, "use_lift", 0))
     P.use_eilers = int(getattr(prm, "use_eilers", 0))
     P.use_les = int(getattr(prm, "use_les", 0))
+    P.lub_contact = int(getattr(prm, "lub_contact", 1))
     return P
 
 

@@ -92,3 +92,13 @@ def test_dem_roofline_counts_pair_flops(bench):
     assert r["frac"] == pytest.approx(r["achieved"] / 78.6, rel=1e-3)
     h = bench.roofline_entry("integrate", times, kb, "none", None, 1e9)
     assert h["bound"] == "hbm" and h["achieved"] == pytest.approx(8e6 / 0.5e-3 / 1e9)
+
+
+def test_richardson_zaki_correlation(bench):
+    """Sec. 4 correlation: kappa per Reynolds-number branch; at Re_T = 16.8
+    and <eps_p> = 0.3 the prediction is 0.302 (evaluated by hand)."""
+    assert bench.richardson_zaki(0.5, 0.1) == pytest.approx(0.5 ** 4.65)
+    assert bench.richardson_zaki(0.5, 0.5) == pytest.approx(0.5 ** (4.35 * 0.5 ** -0.03))
+    assert bench.richardson_zaki(0.5, 600.0) == pytest.approx(0.5 ** 2.39)
+    assert bench.richardson_zaki(0.3, 16.8) == pytest.approx(0.302, abs=5e-4)
+    assert bench.richardson_zaki(0.0, 16.8) == 1.0
