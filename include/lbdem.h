@@ -280,13 +280,14 @@ lbdem_status lbdem_set_timing(lbdem_domain_t h, int on);
 lbdem_status lbdem_kernel_time(lbdem_domain_t h, int cls, double *ms_total, int64_t *launches);
 
 /* Pick launch shapes for this domain by timing them on its current state:
- * the gather variant (see lbdem_set_gather_variant) and the processing order
+ * the gather variant (see lbdem_set_gather_variant), the processing order
  * of the DEM force pass (slot order, or block by block with one of a few
  * block shapes, so that the particles in flight on one XCD cover a compact
- * region whose neighbours stay in its L2 cache). Results are bit-identical
- * across choices: every gather variant sums a cell's particles in the same
- * order, and each particle's DEM force is the same in any processing order.
- * Optional out: the chosen gather variant. */
+ * region whose neighbours stay in its L2 cache) and the residency of the
+ * streaming cell passes. Results are bit-identical across choices: every
+ * gather variant sums a cell's particles in the same order, each particle's
+ * DEM force is the same in any processing order, and the cell passes are
+ * cell-local. Optional out: the chosen gather variant. */
 lbdem_status lbdem_autotune(lbdem_domain_t h, int32_t *gather_variant);
 
 /* Launch choices of a domain (autotuned or set by hand). */
@@ -296,6 +297,10 @@ typedef struct lbdem_tuning {
                                  particles on), 0 slot order, 1 blocked order */
     int32_t dem_block[3];     /* block shape of the blocked order in cells, 1..256 each
                                  (default 32 x 32 x 32) */
+    int32_t cell_waves;       /* workgroups of 256 threads per CU for the streaming
+                                 cell passes (moments, stream-collide), capped with
+                                 reserved LDS: -1 default (4 for FP32 storage, none
+                                 for FP64), 0 no cap, 1..16 */
 } lbdem_tuning;
 
 /* Read the domain's launch choices. */

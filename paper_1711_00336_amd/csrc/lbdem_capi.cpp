@@ -59,7 +59,7 @@ struct lbdem_domain {
     int device = 0;             // the HIP device current at creation
     Geo geo{};
     Phys phys{};
-    Tune tune{-1, -1};
+    Tune tune{-1, -1, -1};
     int64_t version = 0;        // bumped whenever the particle set is replaced
     std::string err;
     int64_t step_host = 0;
@@ -1392,6 +1392,37 @@ static void autotune_impl(lbdem_domain_t h)
         launch_dem_order(h->desc(), h->stream);
         hip_check(hipStreamSynchronize(h->stream), "sync");
     }
+
+    // residency of the streaming cell passes, timed on the moments pass and
+    // the stream-collide (both rewrite the same outputs from the same inputs;
+    // the stream-collide's step count is restored afterwards)
+    {
+        const int cand[] = {-1, 0, 3, 4, 5, 6};
+        float best_t = 1e30f;
+        int best = -1;
+        const Cells<R> C = h->cells<R>();
+        for (int cw : cand) {
+            h->tune.cell_waves = cw;
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 4; ++rep) {
+                hip_check(hipEventRecord(a, h->stream), "hipEventRecord");
+                launch_moments<R>(h->desc(), C, h->stream);
+                launch_stream_collide<R>(h->desc(), C, h->stream);
+                hip_check(hipEventRecord(b, h->stream), "hipEventRecord");
+                hip_check(hipEventSynchronize(b), "hipEventSynchronize");
+                float ms = 0.f;
+                hip_check(hipEventElapsedTime(&ms, a, b), "hipEventElapsedTime");
+                if (rep > 0) tmin = std::min(tmin, ms);
+            }
+            if (tmin < 0.97f * best_t) {
+                best_t = tmin;
+                best = cw;
+            }
+        }
+        h->tune.cell_waves = best;
+        launch_set_step(h->stepc, (long long)h->step_host, h->stream);
+        hip_check(hipStreamSynchronize(h->stream), "sync");
+    }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     h->drop_graphs();
@@ -1417,6 +1448,7 @@ lbdem_status lbdem_get_tuning(lbdem_domain_t h, lbdem_tuning *out)
     out->gather_variant = h->tune.gather;
     out->dem_order = h->tune.dem_order;
     for (int a = 0; a < 3; ++a) out->dem_block[a] = h->ord.ob[a];
+    out->cell_waves = h->tune.cell_waves;
     return LBDEM_OK;
 }
 
@@ -1426,6 +1458,8 @@ lbdem_status lbdem_set_tuning(lbdem_domain_t h, const lbdem_tuning *t)
     if (t->gather_variant < -1 || t->gather_variant >= kGatherVariants)
         return fail(h, LBDEM_E_INVALID, "unknown gather variant");
     if (t->dem_order < -1 || t->dem_order > 1) return fail(h, LBDEM_E_INVALID, "dem_order must be -1, 0 or 1");
+    if (t->cell_waves < -1 || t->cell_waves > 16)
+        return fail(h, LBDEM_E_INVALID, "cell_waves must be -1 (default), 0 (no cap) or 1..16");
     for (int a = 0; a < 3; ++a)
         if (t->dem_block[a] < 1 || t->dem_block[a] > 256)
             return fail(h, LBDEM_E_INVALID, "DEM block edges must be in 1..256 cells");
@@ -1433,6 +1467,7 @@ lbdem_status lbdem_set_tuning(lbdem_domain_t h, const lbdem_tuning *t)
         hip_check(hipStreamSynchronize(h->stream), "sync");
         h->tune.gather = t->gather_variant;
         h->tune.dem_order = t->dem_order;
+        h->tune.cell_waves = t->cell_waves;
         set_order_shape(h, t->dem_block[0], t->dem_block[1], t->dem_block[2]);
         launch_dem_order(h->desc(), h->stream);
         hip_check(hipStreamSynchronize(h->stream), "sync");

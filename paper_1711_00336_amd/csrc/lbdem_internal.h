@@ -109,6 +109,8 @@ struct Parts {
 struct Tune {
     int gather;                 // -1 by density; 0/1/2/4 LDS tiles 16x4x8, 16x4x4, 8x4x4, 16x4x16; 3 per cell
     int dem_order;              // 0: DEM force pass in slot order; 1: in the blocked order of Order
+    int cell_waves;             // workgroups per CU of the streaming cell passes (moments, stream-collide):
+                                // 0 unlimited, else capped through reserved LDS; -1 default
 };
 
 // Processing order of the DEM force pass. Slots are sorted by cell in

@@ -2056,9 +2056,19 @@ static inline unsigned grid_stride_blocks(int64_t n)
     return (unsigned)b;
 }
 
+// Residency of the streaming cell passes: unused dynamic LDS caps the
+// workgroups per CU (160 KB of LDS per CU); -1 is the measured default (4
+// workgroups of 256 threads, 4 waves per SIMD, for the FP32 stream-collide)
+static inline unsigned cell_lds_bytes(int cell_waves, unsigned dflt)
+{
+    if (cell_waves < 0) return dflt;
+    if (cell_waves == 0) return 0u;
+    return (160u * 1024u / (unsigned)cell_waves) & ~255u;
+}
 template <typename R> void launch_moments(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_moments<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), 0, s, D, C);
+    hipLaunchKernelGGL(k_moments<R>, dim3(nblocks(D.g.nc)), dim3(kBlock), cell_lds_bytes(D.t.cell_waves, 0u), s, D,
+                       C);
 }
 template <typename R> void launch_cellfields(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
@@ -2166,7 +2176,7 @@ template <typename R> void launch_gather_eps_am(const Desc &D, const Cells<R> &C
 // 3 1.33 ms. The FP64 instances already run at 4 and 3 waves per SIMD.
 template <typename R> void launch_stream_collide(const Desc &D, const Cells<R> &C, hipStream_t s)
 {
-    constexpr unsigned lds = sizeof(R) == 4 ? 40000u : 0u;
+    const unsigned lds = cell_lds_bytes(D.t.cell_waves, sizeof(R) == 4 ? 40000u : 0u);
     if (D.p.use_eilers || D.p.use_les)
         hipLaunchKernelGGL((k_stream_collide<R, true>), dim3(nblocks(D.g.nc)), dim3(kBlock), lds, s, D, C);
     else

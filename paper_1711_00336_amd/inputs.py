@@ -453,7 +453,17 @@ def case_sphere_wall(d=0.5, rho_ratio=192.0, g=1e-4, tau=0.51, n=None, z0=None, 
     return Case(f"sphere-wall-{n[0]}x{n[1]}x{n[2]}-d{d}-rho{rho_ratio:g}", p, parts, 0)
 
 
-def case_hindered_settling(seed, eps_p, d=0.5, tau=0.505, g=9.35e-3, edge_d=32, use_les=1, precision="fp64",
+def glass_in_water_gravity(tau, d=0.5):
+    """Lattice gravity of the paper's glass spheres in water (d_p = 0.35 mm
+    resolved by d cells, nu = 1e-6 m^2/s, g = 9.81 m/s^2) at relaxation time
+    tau: dx = 0.35 mm / d, dt = nu_lat dx^2 / nu with nu_lat = (tau - 1/2)/3,
+    g_lat = g dt^2 / dx. A unit conversion only."""
+    dx = 0.35e-3 / d
+    dt = (tau - 0.5) / 3.0 * dx * dx / 1e-6
+    return 9.81 * dt * dt / dx
+
+
+def case_hindered_settling(seed, eps_p, d=0.5, tau=0.505, g=None, edge_d=32, use_les=1, precision="fp64",
                            n_int=10, n_dem=50):
     """Hindered settling (Sec. 4.1 Setup): a fully periodic cube of edge_d
     diameters, uniform spheres at solid fraction eps_p (eps_p = 0: a single
@@ -463,9 +473,19 @@ def case_hindered_settling(seed, eps_p, d=0.5, tau=0.505, g=9.35e-3, edge_d=32, 
     spheres in water (d = 0.35 mm = d cells, nu = 1e-6 m^2/s, g = 9.81 m/s^2)
     to lattice units at tau = 0.505: dx = 0.7 mm, dt = nu_lat dx^2/nu =
     0.817 ms, g dt^2/dx = 9.35e-3, with the Smagorinsky model on as in the
-    paper's baseline."""
+    paper's baseline (g = None: glass_in_water_gravity(tau, d)).
+
+    The fluid body force balances the spheres' submerged weight exactly:
+    f_b = -sum_p (rho_p - rho_f) V_p g / sum_x eps_f, applied as eps_f f_b.
+    The printed f_b = -<eps_p> (rho_p - rho_f) g leaves a net force of
+    <eps_p>^2 (rho_p - rho_f) g per volume, under which the whole suspension
+    drifts by ~30 <eps_p>^2 rho_p f(eps_p) u_pT over the 30 t_St of the
+    protocol: ~30 u_pT at <eps_p> = 0.3, beyond the Mach limit at this
+    Reynolds number."""
     n = int(round(edge_d * d))
-    p = Params(n=(n, n, n), periodic=(1, 1, 1), tau=tau, gravity=(0.0, 0.0, -abs(g)), body_force_auto=1,
+    if g is None:
+        g = glass_in_water_gravity(tau, d)
+    p = Params(n=(n, n, n), periodic=(1, 1, 1), tau=tau, gravity=(0.0, 0.0, -abs(g)), body_force_auto=0,
                e_n=0.88, mu_c=0.25, T_c=0.5, h_c=d, n_int=n_int, n_dem=n_dem, use_les=use_les, precision=precision)
     if eps_p <= 0.0:
         c = 0.5 * n
@@ -473,6 +493,9 @@ def case_hindered_settling(seed, eps_p, d=0.5, tau=0.505, g=9.35e-3, edge_d=32, 
                           np.array([float(d)]), np.array([2.5]))
     else:
         parts = make_particles(seed, p, count_for_fraction(eps_p, n ** 3, d), d, d, 2.5)
+    vol = float(np.sum(np.pi / 6.0 * parts.d ** 3))
+    weight = float(np.sum((parts.rho_p - p.rho_f) * np.pi / 6.0 * parts.d ** 3))
+    p.body_force = (0.0, 0.0, weight * abs(g) / (n ** 3 - vol))
     return Case(f"hindered-{n}^3-eps{eps_p:.2f}", p, parts, seed)
 
 

@@ -171,3 +171,43 @@ def test_server_unstable_request_fails_alone(L):
     assert rb["status"] == L.E_UNSTABLE and rb["steps_done"] < 300
     assert rg["status"] == 0 and rg["u_ps"] == alone["u_ps"]
     assert st["active"] == 0 and st["queued"] == 0 and st["bytes"] == 0
+
+
+def test_served_results_match_the_fp64_oracle(L):
+    """Served FP32-deviation solves against the FP64 oracle on a sample of
+    small requests (edges 16-20, solid fractions 0.05-0.2, the serving tau),
+    served together in one mix: <u_pS> sampled at the same chunk ends within
+    the FP32 settling tolerance (1e-3 relative), <eps_f> within 1e-6, total
+    momentum within 1e-6 of sum m|u_p| + sum rho|u_bar|."""
+    from oracle import oracle as O
+    reqs = [I.case_settling(61, 16, 0.1, 0.8, 2.5, precision="fp32dev", tau=I.SWEEP_TAU),
+            I.case_settling(62, 20, 0.05, 0.7, 2.0, precision="fp32dev", tau=I.SWEEP_TAU),
+            I.case_settling(63, 18, 0.2, 0.9, 3.0, precision="fp32dev", tau=I.SWEEP_TAU)]
+    steps, avg_from, chunk = 120, 40, 20
+    _say("served mix of " + ", ".join(f"{c.name} ({c.particles.n} spheres)" for c in reqs))
+    with L.Server(8 << 30, max_slots=8, chunk_steps=chunk) as srv:
+        tks = [srv.lbdem_server_submit(c.params, c.particles, steps, avg_from) for c in reqs]
+        got = [srv.wait(t) for t in tks]
+    for c, g in zip(reqs, got):
+        assert g["status"] == 0 and g["steps_done"] == steps
+        o = O.Oracle(c.params.copy(precision="fp64"), c.particles)
+        s, n, done = 0.0, 0, 0
+        while done < steps:
+            r = o.step(chunk)
+            assert r["status"] == 0
+            done += chunk
+            if done > avg_from:
+                s += o.diagnostics()["u_ps"]
+                n += 1
+        ups_o = s / n
+        do = o.diagnostics()
+        m = c.particles.rho_p * np.pi * c.particles.d ** 3 / 6
+        aux = o.step(1, aux=True)  # one more step only for the fluid momentum scale
+        scale = float(np.sum(m * np.linalg.norm(o.state.u, axis=1))
+                      + np.sum(np.linalg.norm(aux["j"] + 0.5 * aux["f_acc"], axis=0)))
+        e_ups = abs(g["u_ps"] - ups_o) / abs(ups_o)
+        e_eps = abs(g["mean_eps_f"] - do["mean_eps_f"]) / do["mean_eps_f"]
+        e_mom = float(np.abs(np.asarray(g["mom"]) - (do["mom_fluid"] + do["mom_part"])).max()) / scale
+        _say(f"  {c.name}: <u_pS> served {g['u_ps']:.6e} oracle {ups_o:.6e} rel {e_ups:.2e}; "
+             f"<eps_f> rel {e_eps:.2e}; momentum rel {e_mom:.2e}")
+        assert e_ups <= 1e-3 and e_eps <= 1e-6 and e_mom <= 1e-6
