@@ -79,8 +79,11 @@ typedef struct lbdem_params {
     double T_c;              /* collision time; <= 0 selects 20 DEM substeps (Eq. collision_time) */
     double h_c;              /* lubrication cut-off gap (Sec. 3.1.3) */
     double h_min;            /* lower gap limit, 1e-5 (Sec. 3.1.3) */
-    int32_t lub_stab;        /* 1: also floor the gap where the explicit squeeze
-                                force would overshoot: 3 pi mu <d>^2 dt_DEM / (8 m_ij) */
+    int32_t lub_stab;        /* 1: also floor the gap at 3 pi mu <d>^2 dt_DEM / (2 m_ij),
+                                where the leading squeeze term relaxes a pair's
+                                relative velocity by a quarter per DEM substep:
+                                the explicit update then stays stable for a sphere
+                                with a full shell of near-touching partners */
     int32_t use_lub;         /* lubrication on/off */
     int32_t use_am;          /* added mass on/off */
     int32_t n_int;           /* interaction subcycles per LBM step (Alg. 1) */

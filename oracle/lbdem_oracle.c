@@ -564,9 +564,13 @@ static void contact(const orc_params *p, double delta, const double n[3], const 
 
 /* Eq. lubrication_force for sphere i; only if h < h_c; h := max(h, h_min).
  * Reading (explicit stability): the gap is also floored at
- * h_stab = 3 pi mu dm^2 dt_DEM / (8 m_ij), where the leading term of a_sq
- * makes a_sq dt_DEM / m_ij = 1; below it the explicit update of the squeeze
- * force would overshoot. It only acts when lub_stab is set.
+ * h_stab = 3 pi mu dm^2 dt_DEM / (8 r m_ij) with r = 1/4, where the leading
+ * term of a_sq makes a_sq dt_DEM / m_ij = r. A sphere with k partners at
+ * the floor relaxes up to (k + 1)/2 times faster than one pair, and with
+ * the lagged added mass the explicit update stays stable only below
+ * 2 - 2 C_am rho_f / rho_p; r = 1/4 covers a full shell of twelve partners.
+ * (With r = 1 three near-touching partners already diverge: the dilute
+ * 128^3 packing does so in a few steps.) It only acts when lub_stab is set.
  * Reading for overlapping spheres (h <= 0): the text clamps the gap at
  * h_min and applies the force (lub_contact = 1, the default); the collision
  * results of Sec. 5 (a rebound near e_n at large Stokes numbers, Table 3)
@@ -579,7 +583,7 @@ static void lubrication(const orc_params *p, double h, double dm, double mij, co
     if (!p->lub_contact && !(h > 0.0)) return;
     double mu = mu0(p);
     double he = fmax(h, p->h_min);
-    if (p->lub_stab) he = fmax(he, 3.0 * M_PI * mu * dm * dm * dt_dem / (8.0 * mij));
+    if (p->lub_stab) he = fmax(he, 3.0 * M_PI * mu * dm * dm * dt_dem / (8.0 * 0.25 * mij));
     double asq, ash;
     orc_lub_coeffs(he, dm, mu, &asq, &ash);
     double un = dot(upr, n);

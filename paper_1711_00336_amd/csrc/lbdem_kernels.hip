@@ -1162,7 +1162,11 @@ __device__ __forceinline__ void contact(const Phys &p, T delta, const T n[3], co
 }
 
 // Eq. lubrication_force, applied for h < h_c with h := max(h, h_min) and,
-// when lub_stab is set, h >= 3 pi mu <d>^2 dt_DEM / (8 m_ij); inv_dm = 1/<d>.
+// when lub_stab is set, h >= 3 pi mu <d>^2 dt_DEM / (8 r m_ij) with r = 1/4:
+// the leading squeeze term then relaxes one pair by at most a quarter of
+// its relative velocity per substep, so a sphere with a full shell of
+// partners at the floor (up to (12 + 1)/2 times one pair's rate) stays
+// below the explicit limit 2 - 2 C_am rho_f/rho_p; inv_dm = 1/<d>.
 // With lub_contact = 0 only on the open gap (h > 0).
 template <typename T>
 __device__ __forceinline__ void lubrication(const Phys &p, T h, T dm, T inv_dm, T mij, const T n[3], const T upr[3],
@@ -1173,7 +1177,7 @@ __device__ __forceinline__ void lubrication(const Phys &p, T h, T dm, T inv_dm, 
     const T mu = (T)p.mu;
     const T pi = (T)M_PI;
     T he = fmax(h, (T)p.h_min);
-    if (p.lub_stab) he = fmax(he, (T)3 * pi * mu * dm * dm * (T)p.dt_dem * rcp64((T)8 * mij));
+    if (p.lub_stab) he = fmax(he, (T)3 * pi * mu * dm * dm * (T)p.dt_dem * rcp64((T)2 * mij));
     const T inv_he = rcp64(he);
     const T Lg = log(dm * (T)0.5 * inv_he);
     const T asq = (T)1.5 * pi * mu * dm * (dm * (T)0.25 * inv_he + ((T)18 / (T)40) * Lg + ((T)9 / (T)84) * (he * inv_dm) * Lg);

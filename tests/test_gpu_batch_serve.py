@@ -154,7 +154,7 @@ def test_server_cancel(L):
 
 def test_server_unstable_request_fails_alone(L):
     """A request in the unstable corner of the explicit coupling (tau = 0.7,
-    light crowded spheres: the FP64 oracle diverges at step 5 on it) ends
+    light crowded spheres: the FP64 oracle diverges within 50 steps) ends
     with LBDEM_E_UNSTABLE and frees its memory and slot; a request running
     beside it is unaffected (its result equals the same request alone)."""
     bad = I.case_settling(23, 18, 0.3, 0.8, 2.0, precision="fp32dev", tau=0.7)

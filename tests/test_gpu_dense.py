@@ -4,10 +4,20 @@
 identical state.
 
   * 32 x 32 x 64 cells, FP64: every state array within 1e-12 of its largest
-    oracle value (velocities and accelerations as in the other parity tests);
+    oracle value (velocities and accelerations as in the other parity tests).
+    Spins and accelerations of spheres in marginal contact are limited by
+    conditioning rather than by the arithmetic: the contact spring turns the
+    rounding of a position (1 ulp at z ~ 40 is 7e-15) into a force error of
+    k_n ulp(x), independent of the spin's own size. Where the oracle's own
+    result moves by more than the bar when every position is moved by one
+    ulp, those two arrays are held to a tenth of that response instead (the
+    GPU result is then closer to the oracle than the oracle is to itself
+    under an input change invisible in FP64);
   * 64 x 64 x 128 cells, FP32 deviations (pair forces FP64 from packed
     records with FP32 velocities): within 1e-5.
 """
+import copy
+
 import numpy as np
 import pytest
 
@@ -28,23 +38,43 @@ def _say(msg):
     print(msg, flush=True)
 
 
+def _arrays(st):
+    return dict(df=st.df, uprev=st.uprev, x=st.x, u=st.u, w=st.w, a=st.a)
+
+
 @pytest.mark.parametrize("n,precision,tol", [((32, 32, 64), "fp64", 1e-12), ((64, 64, 128), "fp32dev", 1e-5)])
 def test_dense_sub_box_one_step(L, n, precision, tol):
     case = I.case_dense_walled(0, n=n, eps_p=0.4, precision=precision)
     rng = np.random.default_rng(5)
-    # random velocities and spins so that contacts, friction and lubrication
-    # are all active in the compared step
+    # random velocities and spins (a few times the settling speeds of the
+    # workload) so that contacts, friction and lubrication are all active in
+    # the compared step; much faster, more violent random motion makes the
+    # 100 DEM substeps of one step amplify round-off differences chaotically
     case.particles.u[:] = rng.normal(size=case.particles.u.shape) * 1e-3
     case.particles.w[:] = rng.normal(size=case.particles.w.shape) * 1e-3
     _say(f"case {case.name} {precision} np {case.particles.n}")
     o = warm_oracle(case, 1)
+    limits = dict.fromkeys(("df", "uprev", "x", "u", "w", "a"), tol)
+    if precision == "fp64":
+        # the oracle's response to a one-ulp move of every position
+        o1 = copy.deepcopy(o)
+        x, hi = o1.state.x, np.asarray(case.params.n, float)
+        up = np.random.default_rng(7).random(x.shape) < 0.5
+        up = (up | (x == 0.0)) & (np.nextafter(x, np.inf) < hi)
+        x[:] = np.nextafter(x, np.where(up, np.inf, -np.inf))
+        o1.step(1)
     with L.Domain(case.params) as dom:
         load_oracle_state(dom, o.state)
         dom.step(1)
         o.step(1)
-        errs, bad = compare_states(dom.lbdem_get_state(), o.state, case.params, tol)
+        if precision == "fp64":
+            resp, _ = compare_states(_arrays(o1.state), o.state, case.params, tol)
+            _say(f"  oracle response to one ulp of position {resp}")
+            for k in ("w", "a"):
+                limits[k] = max(tol, 0.1 * resp[k])
+        errs, bad = compare_states(dom.lbdem_get_state(), o.state, case.params, limits)
         diag = dom.lbdem_diagnostics()
-    _say(f"  rel errors {errs}")
+    _say(f"  rel errors {errs}; limits {limits}")
     assert not bad, errs
     assert diag["min_eps_f"] > 0.0
 
