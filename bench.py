@@ -139,11 +139,14 @@ def kernel_bytes(case, nlist, dem_order=0):
                       per particle 9 weights + F_d            10 rs + 9 ws + 24 B
       gather_eps      per cell rho, j read, eps_p, f_am, u_f written;
                       per particle 9 weights + d + F_am       11 rs + 9 ws + 32 B
-      nlist           per particle position, diameter, build flag read; a
-                      rebuild writes the list (counted as 0: most launches
-                      only read the flag)                                 0
+      nlist           the neighbours' current slots (n_DEM >= 3): per
+                      particle list length, per entry its label and that
+                      label's slot read, the slot written (a rebuild, which
+                      also reads positions and writes the labels, is rare
+                      and not counted; with n_DEM < 3 the force pass looks
+                      the slots up itself and this is 0)          4 B + 12 L B
       dem_force       per particle x, u, omega, d, rho, id, list length,
-                      L list entries read, F, T written          140 B + 4 L B
+                      L neighbour slots read, F, T written       140 B + 4 L B
       integrate       per particle x, u, omega, F_const, F, T, d, rho,
                       x_start read; x, u, omega written                 256 B
       bins            binning and reordering: per particle position read
@@ -169,7 +172,8 @@ def kernel_bytes(case, nlist, dem_order=0):
             "part_drag": n * (128 + 9 * ws) + nc * 7 * rs,
             "gather_am": nc * 11 * rs + n * (9 * ws + (48 if lift else 24)),
             "gather_fd": nc * 10 * rs + n * (9 * ws + 24),
-            "gather_eps": nc * 11 * rs + n * (9 * ws + 32), "nlist": 0,
+            "gather_eps": nc * 11 * rs + n * (9 * ws + 32),
+            "nlist": int(n * (4 + 12 * nlist)) if case.params.n_dem >= 3 else 0,
             "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * 256,
             "bins": n * (300 + 9 * ws + (64 if fp32 else 0) + (4 if dem_order else 0)) + nc * 20,
             "curl": nc * 6 * rs}

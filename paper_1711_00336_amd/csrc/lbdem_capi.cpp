@@ -354,8 +354,11 @@ void ensure_lists(lbdem_domain_t h)
     need = std::min(std::max((need + 3) & ~3, 32), 4096);
     if (P.nlist && need <= P.nbr && h->nlist_rows >= P.cap) return;
     h->dfree(P.nlist);
+    h->dfree(P.nslot);
+    P.nlist = P.nslot = nullptr;
     P.nbr = std::max(need, P.nbr);
     P.nlist = (int *)h->dalloc(sizeof(int) * (size_t)P.nbr * (size_t)P.cap);
+    P.nslot = (int *)h->dalloc(sizeof(int) * (size_t)P.nbr * (size_t)P.cap);
     h->nlist_rows = P.cap;
 }
 
@@ -462,9 +465,9 @@ void alloc_particles(lbdem_domain_t h, int64_t cap)
         *v = (int *)h->dalloc(sizeof(int) * c);
         hip_check(hipMemsetAsync(*v, 0, sizeof(int) * c, h->stream), "hipMemsetAsync");
     }
-    for (int **v : {&P.nlist, &P.nnb, &P.slot_of}) h->dfree(*v);
+    for (int **v : {&P.nlist, &P.nnb, &P.slot_of, &P.nslot}) h->dfree(*v);
     h->dfree(P.xbuild);
-    P.nlist = nullptr;
+    P.nlist = P.nslot = nullptr;
     P.nbr = 0;
     h->nlist_rows = 0;
     P.nnb = (int *)h->dalloc(sizeof(int) * c);

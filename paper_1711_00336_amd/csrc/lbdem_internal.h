@@ -96,8 +96,10 @@ struct Parts {
     // Verlet lists labelled by the slot a particle had when the lists were
     // built (bslot[slot], carried through the reorders): nlist[label*nbr + t]
     // holds neighbour labels in ascending insertion index, nnb[label] entries,
-    // build positions xbuild[3][cap] by label; slot_of[label] = current slot
-    int *nlist, *nnb, *slot_of;
+    // build positions xbuild[3][cap] by label; slot_of[label] = current slot;
+    // nslot[label*nbr + t] = slot_of[nlist[label*nbr + t]] (t < nnb[label]),
+    // refreshed with the lists at the start of every subcycle when n_DEM >= 3
+    int *nlist, *nnb, *slot_of, *nslot;
     int *bslot, *bslot2;        // label of the particle in each slot (+ permutation target)
     int nbr;                    // list capacity per particle (sized from the density and reach)
     double *xbuild;

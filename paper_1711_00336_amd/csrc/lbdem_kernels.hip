@@ -1128,6 +1128,38 @@ __device__ __forceinline__ double rcp64(double x)
 }
 __device__ __forceinline__ float rcp64(float x) { return 1.0f / x; }
 
+// Natural logarithm of a positive normal double: x = 2^k m with m in
+// [1/sqrt 2, sqrt 2) and ln m = 2 atanh(s), s = (m - 1)/(m + 1), so that
+// |s| <= 3 - 2 sqrt 2 = 0.1716, summed as the Taylor series of atanh through
+// s^19 (the first omitted term is below 3e-17 of the sum). Within 2 ulp of
+// the correctly rounded logarithm; about a third of the instructions of the
+// general library logarithm, which also handles zero, negative, subnormal
+// and non-finite arguments (the lubrication logarithm ln(<d>/2h) only sees
+// gaps h >= h_min > 0).
+__device__ __forceinline__ double log_pos(double x)
+{
+    double m = __builtin_amdgcn_frexp_mant(x);  // x = m 2^k, m in [1/2, 1)
+    int k = __builtin_amdgcn_frexp_exp(x);
+    if (m < M_SQRT1_2) {
+        m += m;
+        --k;
+    }
+    const double s = (m - 1.0) * rcp64(m + 1.0);
+    const double z = s * s;
+    double q = 1.0 / 19.0;
+    q = fma(q, z, 1.0 / 17.0);
+    q = fma(q, z, 1.0 / 15.0);
+    q = fma(q, z, 1.0 / 13.0);
+    q = fma(q, z, 1.0 / 11.0);
+    q = fma(q, z, 1.0 / 9.0);
+    q = fma(q, z, 1.0 / 7.0);
+    q = fma(q, z, 1.0 / 5.0);
+    q = fma(q, z, 1.0 / 3.0);
+    const double t = s + s;
+    return fma((double)k, M_LN2, fma(t * z, q, t));
+}
+__device__ __forceinline__ float log_pos(float x) { return logf(x); }
+
 // spring-dashpot normal force and Coulomb-limited tangential force; torque
 // about the centre is (d_i/2) n x F^t (the moment of F^t at the contact point)
 template <typename T>
@@ -1167,54 +1199,69 @@ __device__ __forceinline__ void contact(const Phys &p, T delta, const T n[3], co
 // its relative velocity per substep, so a sphere with a full shell of
 // partners at the floor (up to (12 + 1)/2 times one pair's rate) stays
 // below the explicit limit 2 - 2 C_am rho_f/rho_p; inv_dm = 1/<d>.
-// With lub_contact = 0 only on the open gap (h > 0).
+// With lub_contact = 0 only on the open gap (h > 0). The reduced mass is
+// passed as m_ij = m_prod / m_sum.
 template <typename T>
-__device__ __forceinline__ void lubrication(const Phys &p, T h, T dm, T inv_dm, T mij, const T n[3], const T upr[3],
-                                            T F[3])
+__device__ __forceinline__ void lubrication(const Phys &p, T h, T dm, T inv_dm, T m_prod, T m_sum, const T n[3],
+                                            const T upr[3], T F[3])
 {
     if (!(h < (T)p.h_c)) return;
     if (!p.lub_contact && !(h > (T)0)) return;  // open gap only
     const T mu = (T)p.mu;
     const T pi = (T)M_PI;
     T he = fmax(h, (T)p.h_min);
-    if (p.lub_stab) he = fmax(he, (T)3 * pi * mu * dm * dm * (T)p.dt_dem * rcp64((T)2 * mij));
-    const T inv_he = rcp64(he);
-    const T Lg = log(dm * (T)0.5 * inv_he);
+    if (p.lub_stab) {
+        // he = max(he, c / (2 m_ij)) with m_ij = m_prod / m_sum, compared
+        // without the division, which only the few pairs at the floor need
+        const T c = (T)3 * pi * mu * dm * dm * (T)p.dt_dem * m_sum;
+        if (he * ((T)2 * m_prod) < c) he = c * rcp64((T)2 * m_prod);
+    }
+    // 1/he and 1/(he + <d>) from one reciprocal
+    const T q = rcp64(he * (he + dm));
+    const T inv_he = (he + dm) * q;
+    const T s = (T)2 * he * q;
+    const T Lg = log_pos(dm * (T)0.5 * inv_he);
     const T asq = (T)1.5 * pi * mu * dm * (dm * (T)0.25 * inv_he + ((T)18 / (T)40) * Lg + ((T)9 / (T)84) * (he * inv_dm) * Lg);
     const T ash = (T)0.5 * pi * mu * dm * Lg * (dm + he) * (dm + he) / (T)4;
     const T un = dot3(upr, n);
-    const T s = (T)2 * rcp64(he + dm);
 #pragma unroll
     for (int a = 0; a < 3; ++a) F[a] += -asq * un * n[a] - ash * s * s * (upr[a] - un * n[a]);
 }
 
-// contact and lubrication of the pair (i, j) at centre offset dx = x_j - x_i,
-// |dx|^2 = dist2 below the interaction reach
+// contact of the pair (i, j) at centre offset dx = x_j - x_i, |dx|^2 =
+// dist2, when the spheres overlap
 template <typename T>
-__device__ __forceinline__ void pair_interaction(const Phys &p, const PV<T> &pi, const PV<T> &pj, const double dx[3],
-                                                 double dist2, T F[3], T Tq[3])
+__device__ __forceinline__ void pair_contact(const Phys &p, const PV<T> &pi, const PV<T> &pj, const double dx[3],
+                                             double dist2, T F[3], T Tq[3])
 {
     const double dist = sqrt(dist2);
+    const T delta = (T)(pi.rr + pj.rr - dist);
+    if (!(delta > (T)0)) return;
     const double inv = rcp64(dist);
     const T n[3] = {(T)(dx[0] * inv), (T)(dx[1] * inv), (T)(dx[2] * inv)};
-    const T delta = (T)(pi.rr + pj.rr - dist);
     const T mij = pi.m * pj.m * rcp64(pi.m + pj.m);
-    if (delta > (T)0) {
-        T s[3], ur[3];
+    T s[3], ur[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) s[a] = pi.r * pi.w[a] + pj.r * pj.w[a];
-        cross3(s, n, ur);
+    for (int a = 0; a < 3; ++a) s[a] = pi.r * pi.w[a] + pj.r * pj.w[a];
+    cross3(s, n, ur);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) ur[a] += pi.u[a] - pj.u[a];
-        contact(p, delta, n, ur, mij, pi.r, F, Tq);
-    }
-    if (p.use_lub) {
-        const T sd = pi.d + pj.d, pd = pi.d * pj.d;
-        const T dm = (T)2 * pd * rcp64(sd);
-        const T inv_dm = (T)0.5 * sd * rcp64(pd);
-        const T upr[3] = {pi.u[0] - pj.u[0], pi.u[1] - pj.u[1], pi.u[2] - pj.u[2]};
-        lubrication(p, -delta, dm, inv_dm, mij, n, upr, F);
-    }
+    for (int a = 0; a < 3; ++a) ur[a] += pi.u[a] - pj.u[a];
+    contact(p, delta, n, ur, mij, pi.r, F, Tq);
+}
+
+// lubrication of the pair (i, j) at centre distance dist (unit normal n,
+// overlap delta = r_i + r_j - dist)
+template <typename T>
+__device__ __forceinline__ void pair_lubrication(const Phys &p, const PV<T> &pi, const PV<T> &pj, const T n[3],
+                                                 T delta, T F[3])
+{
+    // <d> = 2 d_i d_j / (d_i + d_j) and its inverse from one reciprocal
+    const T sd = pi.d + pj.d, pd = pi.d * pj.d;
+    const T q = rcp64(sd * pd);
+    const T dm = (T)2 * pd * pd * q;
+    const T inv_dm = (T)0.5 * sd * sd * q;
+    const T upr[3] = {pi.u[0] - pj.u[0], pi.u[1] - pj.u[1], pi.u[2] - pj.u[2]};
+    lubrication(p, -delta, dm, inv_dm, pi.m * pj.m, pi.m + pj.m, n, upr, F);
 }
 
 template <typename T>
@@ -1236,7 +1283,7 @@ __device__ __forceinline__ void wall_interaction(const Phys &p, const Geo &g, co
                 for (int b = 0; b < 3; ++b) ur[b] += pi.u[b];
                 contact(p, delta, n, ur, pi.m, pi.r, F, Tq);
             }
-            if (p.use_lub) lubrication(p, -delta, (T)2 * pi.d, (T)0.5 * rcp64(pi.d), pi.m, n, pi.u, F);
+            if (p.use_lub) lubrication(p, -delta, (T)2 * pi.d, (T)0.5 * rcp64(pi.d), pi.m, (T)1, n, pi.u, F);
         }
     }
 }
@@ -1393,12 +1440,57 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
     P.slot_of[me] = (int)i;
 }
 
-// contact + lubrication force and torque on every particle from its list.
-// The list is walked in chunks of two entries whose indices, slots and
-// particle data are requested together, so their memory latencies overlap;
-// pairs are still summed in list order.
+// The neighbours' current slots, looked up once per subcycle, after the
+// reordering that closed the last subcycle (and any rebuild), for the n_DEM
+// force passes, which then read each neighbour's record without that
+// dependent load (only with n_DEM >= kNslotMinSubsteps substeps, where that
+// saves more than the lookup pass costs). A workgroup takes kNslotRows list
+// rows, one contiguous run
+// of entries (rows are contiguous by label), and its threads take
+// consecutive entries, so the list reads and slot writes are coalesced; each
+// thread steps its (row, entry) position instead of dividing.
+constexpr int kNslotRows = 64;
+constexpr int kNslotMinSubsteps = 3;
+__host__ __device__ __forceinline__ bool use_nslot(const Desc &D) { return D.p.n_dem >= kNslotMinSubsteps; }
 
-template <typename T, bool REC>
+__global__ __launch_bounds__(kBlock) void k_nslot(Desc D)
+{
+    const Parts &P = D.pt;
+    if (halted(D)) return;
+    const int64_t r0 = (int64_t)blockIdx.x * kNslotRows;
+    const int nrow = (int)min((int64_t)kNslotRows, (int64_t)P.np - r0);
+    const int nbr = P.nbr;
+    const int total = nrow * nbr;
+    const int64_t base = r0 * nbr;
+    const int dr = kBlock / nbr, dt = kBlock - dr * nbr;
+    int row = (int)threadIdx.x / nbr, t = (int)threadIdx.x - row * nbr;
+    for (int e = threadIdx.x; e < total; e += kBlock) {
+        if (t < P.nnb[r0 + row]) P.nslot[base + e] = P.slot_of[P.nlist[base + e]];
+        row += dr;
+        t += dt;
+        if (t >= nbr) {
+            t -= nbr;
+            ++row;
+        }
+    }
+}
+
+// contact + lubrication force and torque on every particle from its list.
+// The list is taken in runs of up to 64 entries. The first pass over a run
+// evaluates the lubrication of every pair within reach and marks the
+// overlapping ones; the second evaluates the contacts of the marked pairs
+// only. Contacts are a small share of the pairs, and evaluated inline the
+// whole wavefront would step through the contact code for almost every
+// entry, since some lane nearly always has an overlap there. In the first
+// pass entries are taken two at a time, their indices, slots and particle
+// data requested together so that the memory latencies overlap. With
+// NSLOT the neighbours' current slots come from the subcycle's refreshed
+// copy of the list (k_nslot), saving a dependent load per neighbour;
+// otherwise they are looked up from the labels here. Both sums
+// run in list order; lubrication, contacts and the walls are summed apart
+// and added at the end.
+
+template <typename T, bool REC, bool NSLOT>
 __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
 {
     const Parts &P = D.pt;
@@ -1408,35 +1500,57 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
     const int64_t i = D.t.dem_order ? (int64_t)D.o.porder[v] : v;
     PV<T> pi;
     load_particle<T, REC>(P, i, pi);
-    T F[3] = {(T)0, (T)0, (T)0}, Tq[3] = {(T)0, (T)0, (T)0};
+    T F[3] = {(T)0, (T)0, (T)0}, Tq[3] = {(T)0, (T)0, (T)0}, Fl[3] = {(T)0, (T)0, (T)0};
     const double gap = D.p.use_lub ? fmax(D.p.h_c, 0.0) : 0.0;
     const int me = P.bslot[i];
     const int n = P.nnb[me];
-    const int *L = P.nlist + (int64_t)me * P.nbr;
+    // the neighbours' slots (NSLOT) or labels, in list order
+    const int *S = (NSLOT ? P.nslot : P.nlist) + (int64_t)me * P.nbr;
     constexpr int kChunk = 2;
-    for (int t0 = 0; t0 < n; t0 += kChunk) {
-        int js[kChunk];
+    for (int s0 = 0; s0 < n; s0 += 64) {
+        const int s1 = min(n, s0 + 64);
+        uint64_t touch = 0;
+        for (int t0 = s0; t0 < s1; t0 += kChunk) {
+            int js[kChunk];
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) js[c] = t0 + c < n ? P.slot_of[L[t0 + c]] : (int)i;
-        PV<T> pj[kChunk];
+            for (int c = 0; c < kChunk; ++c)
+                js[c] = t0 + c < s1 ? (NSLOT ? S[t0 + c] : P.slot_of[S[t0 + c]]) : (int)i;
+            PV<T> pj[kChunk];
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) load_particle<T, REC>(P, js[c], pj[c]);
+            for (int c = 0; c < kChunk; ++c) load_particle<T, REC>(P, js[c], pj[c]);
 #pragma unroll
-        for (int c = 0; c < kChunk; ++c) {
-            if (t0 + c >= n) break;
-            double dx[3] = {pj[c].x[0] - pi.x[0], pj[c].x[1] - pi.x[1], pj[c].x[2] - pi.x[2]};
+            for (int c = 0; c < kChunk; ++c) {
+                if (t0 + c >= s1) break;
+                double dx[3] = {pj[c].x[0] - pi.x[0], pj[c].x[1] - pi.x[1], pj[c].x[2] - pi.x[2]};
+                min_image(D.g, dx);
+                const double reach = pi.rr + pj[c].rr + gap;
+                const double dist2 = dot3(dx, dx);
+                if (dist2 >= reach * reach) continue;
+                const double dist = sqrt(dist2);
+                const T delta = (T)(pi.rr + pj[c].rr - dist);
+                if (delta > (T)0) touch |= 1ull << (t0 + c - s0);
+                if (D.p.use_lub) {
+                    const double inv = rcp64(dist);
+                    const T nv[3] = {(T)(dx[0] * inv), (T)(dx[1] * inv), (T)(dx[2] * inv)};
+                    pair_lubrication(D.p, pi, pj[c], nv, delta, Fl);
+                }
+            }
+        }
+        while (touch) {
+            const int t = __builtin_ctzll(touch);
+            touch &= touch - 1;
+            PV<T> pj;
+            load_particle<T, REC>(P, NSLOT ? S[s0 + t] : P.slot_of[S[s0 + t]], pj);
+            double dx[3] = {pj.x[0] - pi.x[0], pj.x[1] - pi.x[1], pj.x[2] - pi.x[2]};
             min_image(D.g, dx);
-            const double reach = pi.rr + pj[c].rr + gap;
-            const double dist2 = dot3(dx, dx);
-            if (dist2 >= reach * reach) continue;
-            pair_interaction(D.p, pi, pj[c], dx, dist2, F, Tq);
+            pair_contact(D.p, pi, pj, dx, dot3(dx, dx), F, Tq);
         }
     }
     wall_interaction(D.p, D.g, pi, F, Tq);
     const int64_t cap = P.cap;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        P.Fdem[a * cap + i] = (double)F[a];
+        P.Fdem[a * cap + i] = (double)(F[a] + Fl[a]);
         P.Tdem[a * cap + i] = (double)Tq[a];
     }
 }
@@ -2253,8 +2367,15 @@ void launch_diag(const Desc &D, const Cells<R> &C, const R *df, double *partials
 void launch_dem_force(const Desc &D, hipStream_t s)
 {
     if (D.pt.np == 0) return;
-    if (D.pt.pk) hipLaunchKernelGGL((k_dem_force<double, true>), dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
-    else hipLaunchKernelGGL((k_dem_force<double, false>), dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+    const dim3 g(nblocks(D.pt.np)), b(kBlock);
+    const bool ns = use_nslot(D);
+    if (D.pt.pk) {
+        if (ns) hipLaunchKernelGGL((k_dem_force<double, true, true>), g, b, 0, s, D);
+        else hipLaunchKernelGGL((k_dem_force<double, true, false>), g, b, 0, s, D);
+    } else {
+        if (ns) hipLaunchKernelGGL((k_dem_force<double, false, true>), g, b, 0, s, D);
+        else hipLaunchKernelGGL((k_dem_force<double, false, false>), g, b, 0, s, D);
+    }
 }
 void launch_dem_order(const Desc &D, hipStream_t s)
 {
@@ -2266,7 +2387,10 @@ void launch_dem_order(const Desc &D, hipStream_t s)
 }
 void launch_nlist(const Desc &D, hipStream_t s)
 {
-    if (D.pt.np > 0) hipLaunchKernelGGL(k_nlist, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+    if (D.pt.np <= 0) return;
+    hipLaunchKernelGGL(k_nlist, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
+    if (use_nslot(D))
+        hipLaunchKernelGGL(k_nslot, dim3((unsigned)((D.pt.np + kNslotRows - 1) / kNslotRows)), dim3(kBlock), 0, s, D);
 }
 void launch_integrate(const Desc &D, int last, hipStream_t s)
 {

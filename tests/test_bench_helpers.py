@@ -68,6 +68,9 @@ def test_kernel_bytes_per_unit_figures(bench):
     # FP32 form: weights stored as 4-byte floats
     assert kb["gather_eps"] == nc * 11 * 4 + n * (36 + 32)
     assert kb["dem_force"] == n * (140 + 16)
+    # the neighbours' slots are refreshed per subcycle only with n_DEM >= 3
+    assert kb["nlist"] == 0
+    assert bench.kernel_bytes(I.Case("t", prm.copy(n_dem=10), parts, 0), 4.0)["nlist"] == n * (4 + 48)
     assert kb["part_am"] == n * (76 + 36) + nc * 3 * 4
     assert kb["part_drag"] == n * (128 + 36) + nc * 7 * 4
     assert kb["bins"] == n * (300 + 36 + 64) + nc * 20
