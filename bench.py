@@ -148,7 +148,9 @@ def kernel_bytes(case, nlist, dem_order=0):
       dem_force       per particle x, u, omega, d, rho, id, list length,
                       L neighbour slots read, F, T written       140 B + 4 L B
       integrate       per particle x, u, omega, F_const, F, T, d, rho,
-                      x_start read; x, u, omega written                 256 B
+                      x_start, the list's build position and label read;
+                      x, u, omega written; in the FP32 form also the
+                      64-byte DEM record written                 284 B [+ 64 B]
       bins            binning and reordering: per particle position read
                       and bin-list entry (36 B), the bin sort (12 B), the
                       permutation of x, u, omega, a, d, rho, id, label
@@ -174,7 +176,7 @@ def kernel_bytes(case, nlist, dem_order=0):
             "gather_fd": nc * 10 * rs + n * (9 * ws + 24),
             "gather_eps": nc * 11 * rs + n * (9 * ws + 32),
             "nlist": int(n * (4 + 12 * nlist)) if case.params.n_dem >= 3 else 0,
-            "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * 256,
+            "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * (284 + (64 if fp32 else 0)),
             "bins": n * (300 + 9 * ws + (64 if fp32 else 0) + (4 if dem_order else 0)) + nc * 20,
             "curl": nc * 6 * rs}
 

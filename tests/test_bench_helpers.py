@@ -72,6 +72,7 @@ def test_kernel_bytes_per_unit_figures(bench):
     assert kb["nlist"] == 0
     assert bench.kernel_bytes(I.Case("t", prm.copy(n_dem=10), parts, 0), 4.0)["nlist"] == n * (4 + 48)
     assert kb["part_am"] == n * (76 + 36) + nc * 3 * 4
+    assert kb["integrate"] == n * (284 + 64)
     assert kb["part_drag"] == n * (128 + 36) + nc * 7 * 4
     assert kb["bins"] == n * (300 + 36 + 64) + nc * 20
     lift = bench.kernel_bytes(I.Case("t", prm.copy(use_lift=1), parts, 0), 4.0)
@@ -81,6 +82,7 @@ def test_kernel_bytes_per_unit_figures(bench):
     # FP64 weights, no packed DEM records
     assert fp64["part_drag"] == n * 200 + nc * 7 * 8
     assert fp64["bins"] == n * (300 + 72) + nc * 20
+    assert fp64["integrate"] == n * 284
 
 
 def test_dem_roofline_counts_pair_flops(bench):
