@@ -115,7 +115,7 @@ def mean_list_length(case, vskin=0.1, max_query=100000):
     return len(I_) / len(q)
 
 
-def kernel_bytes(case, nlist, dem_order=0):
+def kernel_bytes(case, nlist, dem_order=0, fused=False):
     """Algorithmic HBM bytes per launch of each timed kernel class: what the
     operation must read and write once (re-reads of neighbour cells or
     particles, which a cache can serve, are not counted). rs is the cell
@@ -151,6 +151,10 @@ def kernel_bytes(case, nlist, dem_order=0):
                       x_start, the list's build position and label read;
                       x, u, omega written; in the FP32 form also the
                       64-byte DEM record written                 284 B [+ 64 B]
+      (fused)         with forces and integration of a substep in one pass
+                      (FP32 form, n_DEM >= 3) the dem_force class carries
+                      both without the F, T round trip (2 x 48 B) and
+                      integrate has no launches              392 B + 4 L B
       bins            binning and reordering: per particle position read
                       and bin-list entry (36 B), the bin sort (12 B), the
                       permutation of x, u, omega, a, d, rho, id, label
@@ -176,7 +180,8 @@ def kernel_bytes(case, nlist, dem_order=0):
             "gather_fd": nc * 10 * rs + n * (9 * ws + 24),
             "gather_eps": nc * 11 * rs + n * (9 * ws + 32),
             "nlist": int(n * (4 + 12 * nlist)) if case.params.n_dem >= 3 else 0,
-            "dem_force": int(n * (140 + 4 * nlist)), "integrate": n * (284 + (64 if fp32 else 0)),
+            "dem_force": int(n * ((392 if fused else 140) + 4 * nlist)),
+            "integrate": 0 if fused else n * (284 + (64 if fp32 else 0)),
             "bins": n * (300 + 9 * ws + (64 if fp32 else 0) + (4 if dem_order else 0)) + nc * 20,
             "curl": nc * 6 * rs}
 
@@ -528,14 +533,15 @@ def run_step_workload(lbdem, torch, case, wl_name, K, W, ksteps, stream, args):
     print(f"[bench] mean Verlet-list length {nlist:.2f}, neighbours within reach {nreach:.2f}",
           file=sys.stderr, flush=True)
     dem_order = tuning["dem_order"] if tuning["dem_order"] >= 0 else int(case.particles.n >= 1 << 20)
-    kb = kernel_bytes(case, nlist, dem_order)
+    fused = (tuning.get("fuse_substep", -1) != 0 and case.params.precision == "fp32dev" and case.params.n_dem >= 3)
+    kb = kernel_bytes(case, nlist, dem_order, fused)
     npairs = nreach * case.particles.n
     roofs = {k: roofline_entry(k, times, kb, wl_name, variant, npairs) for k in times
              if times[k]["launches_per_step"] > 0}
     roofs = {k: v for k, v in roofs.items() if v is not None}
     dom_cls = max(roofs, key=lambda k: times[k]["ms_per_step"])
     return dict(nc=nc, dt=dt, variant=variant, times=times, roofs=roofs, dominant=dom_cls, diag=diag,
-                nlist=nlist, nreach=nreach, tuning=dict(tuning, dem_order_resolved=dem_order))
+                nlist=nlist, nreach=nreach, tuning=dict(tuning, dem_order_resolved=dem_order, fused=fused))
 
 
 def richardson_zaki(eps, re_t):
@@ -801,6 +807,7 @@ def main():
                    "pdf_storage": "f32 deviation" if case.params.precision == "fp32dev" else "f64 deviation",
                    "particle_integration": "f64", "tau": case.params.tau, "gather_variant": r["variant"],
                    "dem_order": r["tuning"]["dem_order_resolved"], "dem_block": list(r["tuning"]["dem_block"]),
+                   "dem_substep_fused": r["tuning"]["fused"],
                    "lift": bool(args.lift), "eilers_les": bool(args.visc),
                    "mean_list_length": round(r["nlist"], 2), "neighbours_within_reach": round(r["nreach"], 2)},
         "roofline": roofs[r["dominant"]],

@@ -304,6 +304,13 @@ typedef struct lbdem_tuning {
                                  cell passes (moments, stream-collide), capped with
                                  reserved LDS: -1 default (4 for FP32 storage, none
                                  for FP64), 0 no cap, 1..16 */
+    int32_t fuse_substep;     /* FP32 storage with n_DEM >= 3: the contact and
+                                 lubrication forces of a DEM substep and its
+                                 integration (Sec. 3.1.1) in one pass, the packed
+                                 records alternating between two buffers; -1 default
+                                 (on), 0 off (separate passes), 1 on. Results are
+                                 bit-identical either way; ignored where the form
+                                 does not allow it (FP64 storage, fewer substeps) */
 } lbdem_tuning;
 
 /* Read the domain's launch choices. */

@@ -59,7 +59,7 @@ struct lbdem_domain {
     int device = 0;             // the HIP device current at creation
     Geo geo{};
     Phys phys{};
-    Tune tune{-1, -1, -1};
+    Tune tune{-1, -1, -1, -1};
     int64_t version = 0;        // bumped whenever the particle set is replaced
     std::string err;
     int64_t step_host = 0;
@@ -681,9 +681,15 @@ void enqueue_step(lbdem_domain_t h)
         launch_cls(h, 4, [&] { launch_part_drag<R>(h->desc(), C, last_sub, s); });
         launch_cls(h, 6, [&] { launch_gather_fd<R>(h->desc(), C, s); });
         launch_cls(h, 8, [&] { launch_nlist(h->desc(), s); });
+        const bool fused = dem_substep_fused(h->desc());
         for (int sub = 0; sub < h->phys.n_dem; ++sub) {
-            launch_cls(h, 9, [&] { launch_dem_force(h->desc(), s); });
-            launch_cls(h, 10, [&] { launch_integrate(h->desc(), sub == h->phys.n_dem - 1, s); });
+            const int last_dem = sub == h->phys.n_dem - 1;
+            if (fused) {
+                launch_cls(h, 9, [&] { launch_dem_substep_fused(h->desc(), sub, last_dem, s); });
+            } else {
+                launch_cls(h, 9, [&] { launch_dem_force(h->desc(), s); });
+                launch_cls(h, 10, [&] { launch_integrate(h->desc(), last_dem, s); });
+            }
         }
         // without lift the next subcycle's added mass is evaluated in the
         // reordering pass, which holds every particle's new stencil
@@ -1452,6 +1458,7 @@ lbdem_status lbdem_get_tuning(lbdem_domain_t h, lbdem_tuning *out)
     out->dem_order = h->tune.dem_order;
     for (int a = 0; a < 3; ++a) out->dem_block[a] = h->ord.ob[a];
     out->cell_waves = h->tune.cell_waves;
+    out->fuse_substep = h->tune.fuse;
     return LBDEM_OK;
 }
 
@@ -1466,11 +1473,14 @@ lbdem_status lbdem_set_tuning(lbdem_domain_t h, const lbdem_tuning *t)
     for (int a = 0; a < 3; ++a)
         if (t->dem_block[a] < 1 || t->dem_block[a] > 256)
             return fail(h, LBDEM_E_INVALID, "DEM block edges must be in 1..256 cells");
+    if (t->fuse_substep < -1 || t->fuse_substep > 1)
+        return fail(h, LBDEM_E_INVALID, "fuse_substep must be -1, 0 or 1");
     return guarded(h, [&]() -> lbdem_status {
         hip_check(hipStreamSynchronize(h->stream), "sync");
         h->tune.gather = t->gather_variant;
         h->tune.dem_order = t->dem_order;
         h->tune.cell_waves = t->cell_waves;
+        h->tune.fuse = t->fuse_substep;
         set_order_shape(h, t->dem_block[0], t->dem_block[1], t->dem_block[2]);
         launch_dem_order(h->desc(), h->stream);
         hip_check(hipStreamSynchronize(h->stream), "sync");

@@ -1475,6 +1475,66 @@ __global__ __launch_bounds__(kBlock) void k_nslot(Desc D)
     }
 }
 
+// One semi-implicit Euler substep of particle i (R5: u and omega first,
+// then x) under the contact and lubrication force F and torque Tq of the
+// substep and the subcycle's frozen F_const, with the wall, skin and
+// finiteness checks; rec: where the particle's new DEM record goes (none
+// after the last substep of a subcycle, whose reorder rewrites every record).
+__device__ __forceinline__ void integrate_particle(const Desc &D, int64_t i, int last, const double F[3],
+                                                   const double Tq[3], DemRec *rec)
+{
+    const Parts &P = D.pt;
+    const int64_t cap = P.cap;
+    const double d = P.d[i];
+    const double m = P.rho[i] * sphere_volume(d);
+    const double I = m * d * d / 10.0;
+    const double dt = D.p.dt_dem;
+    double x[3];
+    int bad = 0;
+    double moved = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int64_t k = a * cap + i;
+        const double u = P.u[k] + dt * (P.Fc[k] + F[a]) / m;
+        P.u[k] = u;
+        P.w[k] = P.w[k] + dt * Tq[a] / I;
+        double xa = P.x[k] + dt * u;
+        const double L = (double)D.g.n[a];
+        if (D.g.per[a]) {
+            if (xa >= L) xa -= L;
+            else if (xa < 0.0) {
+                xa += L;
+                if (xa >= L) xa = 0.0;
+            }
+        } else if (!(xa > 0.0 && xa < L)) {
+            bad |= FLAG_WALL;
+        }
+        if (!isfinite(xa) || !isfinite(u)) bad |= FLAG_NONFINITE;
+        P.x[k] = xa;
+        x[a] = xa;
+        double dx = xa - P.xstart[k];
+        if (D.g.per[a]) dx -= L * rint(dx / L);
+        if (fabs(dx) > D.p.skin) bad |= FLAG_SKIN;
+        if (last) P.a[k] = (u - P.ustart[k]) / D.p.dt_int;
+        if (last) {
+            double db = xa - P.xbuild[a * cap + P.bslot[i]];
+            if (D.g.per[a]) db -= L * rint(db / L);
+            moved = fmax(moved, fabs(db));
+        }
+    }
+    if (bad) atomicOr(D.flags, bad);
+    // the record feeds the next substep's pair loop
+    if (rec && !last) {
+        const double uu[3] = {P.u[i], P.u[cap + i], P.u[2 * cap + i]};
+        const double ww[3] = {P.w[i], P.w[cap + i], P.w[2 * cap + i]};
+        store_rec(rec, i, x, uu, ww, d, P.rho[i]);
+    }
+    // with at most `skin` per subcycle, rebuilding once any particle has moved
+    // vskin/2 - skin keeps every pair within the list reach until the rebuild
+    if (last && moved > 0.5 * D.p.vskin - D.p.skin) *P.need = 1;
+    if (last) atomicAdd(&D.b.cnt[particle_cell(D.g, x[0], x[1], x[2])], 1);
+}
+
 // contact + lubrication force and torque on every particle from its list.
 // The list is taken in runs of up to 64 entries. The first pass over a run
 // evaluates the lubrication of every pair within reach and marks the
@@ -1490,16 +1550,22 @@ __global__ __launch_bounds__(kBlock) void k_nslot(Desc D)
 // run in list order; lubrication, contacts and the walls are summed apart
 // and added at the end.
 
-template <typename T, bool REC, bool NSLOT>
-__global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
+template <typename T, bool REC, bool NSLOT, bool FUSE>
+__global__ __launch_bounds__(kBlock) void k_dem_force(Desc D, int last, int odd)
 {
+    static_assert(!FUSE || REC, "the fused substep reads packed records only");
     const Parts &P = D.pt;
     const int64_t v = gidx();
     if (v == 0) *P.need = 0;  // lists are current for this subcycle
     if (v >= P.np) return;
     const int64_t i = D.t.dem_order ? (int64_t)D.o.porder[v] : v;
+    // FUSE: substeps alternate between the two record buffers, reading the
+    // records of the substep's start and writing the integrated ones to the
+    // other buffer, so that no thread sees another's update
+    const DemRec *src = FUSE && odd ? P.pk2 : P.pk;
     PV<T> pi;
-    load_particle<T, REC>(P, i, pi);
+    if constexpr (REC) load_rec(src, i, pi);
+    else load_pv(P, i, pi);
     T F[3] = {(T)0, (T)0, (T)0}, Tq[3] = {(T)0, (T)0, (T)0}, Fl[3] = {(T)0, (T)0, (T)0};
     const double gap = D.p.use_lub ? fmax(D.p.h_c, 0.0) : 0.0;
     const int me = P.bslot[i];
@@ -1517,7 +1583,10 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
                 js[c] = t0 + c < s1 ? (NSLOT ? S[t0 + c] : P.slot_of[S[t0 + c]]) : (int)i;
             PV<T> pj[kChunk];
 #pragma unroll
-            for (int c = 0; c < kChunk; ++c) load_particle<T, REC>(P, js[c], pj[c]);
+            for (int c = 0; c < kChunk; ++c) {
+                if constexpr (REC) load_rec(src, js[c], pj[c]);
+                else load_pv(P, js[c], pj[c]);
+            }
 #pragma unroll
             for (int c = 0; c < kChunk; ++c) {
                 if (t0 + c >= s1) break;
@@ -1540,7 +1609,9 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
             const int t = __builtin_ctzll(touch);
             touch &= touch - 1;
             PV<T> pj;
-            load_particle<T, REC>(P, NSLOT ? S[s0 + t] : P.slot_of[S[s0 + t]], pj);
+            const int64_t j = NSLOT ? S[s0 + t] : P.slot_of[S[s0 + t]];
+            if constexpr (REC) load_rec(src, j, pj);
+            else load_pv(P, j, pj);
             double dx[3] = {pj.x[0] - pi.x[0], pj.x[1] - pi.x[1], pj.x[2] - pi.x[2]};
             min_image(D.g, dx);
             pair_contact(D.p, pi, pj, dx, dot3(dx, dx), F, Tq);
@@ -1548,10 +1619,16 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D)
     }
     wall_interaction(D.p, D.g, pi, F, Tq);
     const int64_t cap = P.cap;
+    const double Fs[3] = {(double)(F[0] + Fl[0]), (double)(F[1] + Fl[1]), (double)(F[2] + Fl[2])};
+    const double Ts[3] = {(double)Tq[0], (double)Tq[1], (double)Tq[2]};
+    if constexpr (FUSE) {
+        integrate_particle(D, i, last, Fs, Ts, odd ? P.pk : P.pk2);
+    } else {
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        P.Fdem[a * cap + i] = (double)(F[a] + Fl[a]);
-        P.Tdem[a * cap + i] = (double)Tq[a];
+        for (int a = 0; a < 3; ++a) {
+            P.Fdem[a * cap + i] = Fs[a];
+            P.Tdem[a * cap + i] = Ts[a];
+        }
     }
 }
 
@@ -1639,55 +1716,9 @@ __global__ __launch_bounds__(kBlock) void k_integrate(Desc D, int last)
     const Parts &P = D.pt;
     if (i >= P.np) return;
     const int64_t cap = P.cap;
-    const double d = P.d[i];
-    const double m = P.rho[i] * sphere_volume(d);
-    const double I = m * d * d / 10.0;
-    const double dt = D.p.dt_dem;
-    double x[3];
-    int bad = 0;
-    double moved = 0.0;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int64_t k = a * cap + i;
-        const double u = P.u[k] + dt * (P.Fc[k] + P.Fdem[k]) / m;
-        P.u[k] = u;
-        P.w[k] = P.w[k] + dt * P.Tdem[k] / I;
-        double xa = P.x[k] + dt * u;
-        const double L = (double)D.g.n[a];
-        if (D.g.per[a]) {
-            if (xa >= L) xa -= L;
-            else if (xa < 0.0) {
-                xa += L;
-                if (xa >= L) xa = 0.0;
-            }
-        } else if (!(xa > 0.0 && xa < L)) {
-            bad |= FLAG_WALL;
-        }
-        if (!isfinite(xa) || !isfinite(u)) bad |= FLAG_NONFINITE;
-        P.x[k] = xa;
-        x[a] = xa;
-        double dx = xa - P.xstart[k];
-        if (D.g.per[a]) dx -= L * rint(dx / L);
-        if (fabs(dx) > D.p.skin) bad |= FLAG_SKIN;
-        if (last) P.a[k] = (u - P.ustart[k]) / D.p.dt_int;
-        if (last) {
-            double db = xa - P.xbuild[a * cap + P.bslot[i]];
-            if (D.g.per[a]) db -= L * rint(db / L);
-            moved = fmax(moved, fabs(db));
-        }
-    }
-    if (bad) atomicOr(D.flags, bad);
-    // the record feeds the next substep's pair loop; after the last substep
-    // of a subcycle the reorder rewrites every record
-    if (P.pk && !last) {
-        const double uu[3] = {P.u[i], P.u[cap + i], P.u[2 * cap + i]};
-        const double ww[3] = {P.w[i], P.w[cap + i], P.w[2 * cap + i]};
-        store_rec(P.pk, i, x, uu, ww, d, P.rho[i]);
-    }
-    // with at most `skin` per subcycle, rebuilding once any particle has moved
-    // vskin/2 - skin keeps every pair within the list reach until the rebuild
-    if (last && moved > 0.5 * D.p.vskin - D.p.skin) *P.need = 1;
-    if (last) atomicAdd(&D.b.cnt[particle_cell(D.g, x[0], x[1], x[2])], 1);
+    const double F[3] = {P.Fdem[i], P.Fdem[cap + i], P.Fdem[2 * cap + i]};
+    const double Tq[3] = {P.Tdem[i], P.Tdem[cap + i], P.Tdem[2 * cap + i]};
+    integrate_particle(D, i, last, F, Tq, P.pk);
 }
 
 __global__ __launch_bounds__(kBlock) void k_bin_count(Desc D)
@@ -2370,12 +2401,19 @@ void launch_dem_force(const Desc &D, hipStream_t s)
     const dim3 g(nblocks(D.pt.np)), b(kBlock);
     const bool ns = use_nslot(D);
     if (D.pt.pk) {
-        if (ns) hipLaunchKernelGGL((k_dem_force<double, true, true>), g, b, 0, s, D);
-        else hipLaunchKernelGGL((k_dem_force<double, true, false>), g, b, 0, s, D);
+        if (ns) hipLaunchKernelGGL((k_dem_force<double, true, true, false>), g, b, 0, s, D, 0, 0);
+        else hipLaunchKernelGGL((k_dem_force<double, true, false, false>), g, b, 0, s, D, 0, 0);
     } else {
-        if (ns) hipLaunchKernelGGL((k_dem_force<double, false, true>), g, b, 0, s, D);
-        else hipLaunchKernelGGL((k_dem_force<double, false, false>), g, b, 0, s, D);
+        if (ns) hipLaunchKernelGGL((k_dem_force<double, false, true, false>), g, b, 0, s, D, 0, 0);
+        else hipLaunchKernelGGL((k_dem_force<double, false, false, false>), g, b, 0, s, D, 0, 0);
     }
+}
+bool dem_substep_fused(const Desc &D) { return D.pt.pk && use_nslot(D) && D.t.fuse != 0; }
+void launch_dem_substep_fused(const Desc &D, int sub, int last, hipStream_t s)
+{
+    if (D.pt.np == 0) return;
+    hipLaunchKernelGGL((k_dem_force<double, true, true, true>), dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D, last,
+                       sub & 1);
 }
 void launch_dem_order(const Desc &D, hipStream_t s)
 {

@@ -63,7 +63,7 @@ class lbdem_state_view(C.Structure):
 
 class lbdem_tuning(C.Structure):
     _fields_ = [("gather_variant", C.c_int32), ("dem_order", C.c_int32), ("dem_block", C.c_int32 * 3),
-                ("cell_waves", C.c_int32)]
+                ("cell_waves", C.c_int32), ("fuse_substep", C.c_int32)]
 
 
 class lbdem_request(C.Structure):
@@ -330,11 +330,12 @@ class Domain:
         T = lbdem_tuning()
         _check(self.h, lib().lbdem_get_tuning(self.h, C.byref(T)))
         return dict(gather_variant=T.gather_variant, dem_order=T.dem_order, dem_block=tuple(T.dem_block[:]),
-                    cell_waves=T.cell_waves)
+                    cell_waves=T.cell_waves, fuse_substep=T.fuse_substep)
 
-    def lbdem_set_tuning(self, gather_variant=-1, dem_order=-1, dem_block=(32, 32, 32), cell_waves=-1):
+    def lbdem_set_tuning(self, gather_variant=-1, dem_order=-1, dem_block=(32, 32, 32), cell_waves=-1,
+                         fuse_substep=-1):
         T = lbdem_tuning(int(gather_variant), int(dem_order), (C.c_int32 * 3)(*[int(v) for v in dem_block]),
-                         int(cell_waves))
+                         int(cell_waves), int(fuse_substep))
         _check(self.h, lib().lbdem_set_tuning(self.h, C.byref(T)))
 
     def lbdem_autotune(self):

@@ -73,6 +73,8 @@ def test_kernel_bytes_per_unit_figures(bench):
     assert bench.kernel_bytes(I.Case("t", prm.copy(n_dem=10), parts, 0), 4.0)["nlist"] == n * (4 + 48)
     assert kb["part_am"] == n * (76 + 36) + nc * 3 * 4
     assert kb["integrate"] == n * (284 + 64)
+    fz = bench.kernel_bytes(case, 4.0, fused=True)
+    assert fz["dem_force"] == n * (392 + 16) and fz["integrate"] == 0
     assert kb["part_drag"] == n * (128 + 36) + nc * 7 * 4
     assert kb["bins"] == n * (300 + 36 + 64) + nc * 20
     lift = bench.kernel_bytes(I.Case("t", prm.copy(use_lift=1), parts, 0), 4.0)

@@ -85,26 +85,28 @@ def test_dem_processing_orders_bitwise_equal(L, precision):
     shapes that divide the domain and ones that leave partial blocks) gives
     bit-identical states after two coupled steps, and the autotuner's choice
     does too: the order only changes which particles are in flight
-    together, not any particle's sum."""
+    together, not any particle's sum. So does the FP32 form's substep with
+    forces and integration in one pass against the two separate passes."""
     case = I.case_dense_walled(1, n=(40, 36, 52), eps_p=0.4, precision=precision)
     rng = np.random.default_rng(6)
     case.particles.u[:] = rng.normal(size=case.particles.u.shape) * 1e-3
     _say(f"case {case.name} {precision} np {case.particles.n}")
     ref = None
-    for order, block in ((0, (32, 32, 32)), (1, (32, 32, 32)), (1, (16, 8, 4)), (1, (7, 5, 3)), (1, (64, 64, 64)),
-                         ("auto", None)):
+    for order, block, fuse in ((0, (32, 32, 32), -1), (1, (32, 32, 32), -1), (1, (16, 8, 4), -1), (1, (7, 5, 3), -1),
+                               (1, (64, 64, 64), -1), (1, (32, 32, 32), 0), (0, (32, 32, 32), 0), ("auto", None, -1)):
         with L.Domain(case.params) as dom:
             dom.add(case.particles)
             if order == "auto":
                 dom.lbdem_autotune()
                 _say(f"  autotuned {dom.lbdem_get_tuning()}")
             else:
-                dom.lbdem_set_tuning(dem_order=order, dem_block=block)
+                dom.lbdem_set_tuning(dem_order=order, dem_block=block, fuse_substep=fuse)
                 assert dom.lbdem_get_tuning()["dem_block"] == block
+                assert dom.lbdem_get_tuning()["fuse_substep"] == fuse
             dom.step(2)
             st = dom.lbdem_get_state()
         if ref is None:
             ref = st
             continue
         for k in ("df", "x", "u", "w", "a"):
-            assert np.array_equal(ref[k], st[k]), (order, block, k)
+            assert np.array_equal(ref[k], st[k]), (order, block, fuse, k)
