@@ -533,7 +533,7 @@ def run_step_workload(lbdem, torch, case, wl_name, K, W, ksteps, stream, args):
     print(f"[bench] mean Verlet-list length {nlist:.2f}, neighbours within reach {nreach:.2f}",
           file=sys.stderr, flush=True)
     dem_order = tuning["dem_order"] if tuning["dem_order"] >= 0 else int(case.particles.n >= 1 << 20)
-    fused = (tuning.get("fuse_substep", -1) != 0 and case.params.precision == "fp32dev" and case.params.n_dem >= 3)
+    fused = (tuning.get("fuse_substep", -1) == 1 and case.params.precision == "fp32dev" and case.params.n_dem >= 3)
     kb = kernel_bytes(case, nlist, dem_order, fused)
     npairs = nreach * case.particles.n
     roofs = {k: roofline_entry(k, times, kb, wl_name, variant, npairs) for k in times

@@ -308,7 +308,7 @@ typedef struct lbdem_tuning {
                                  lubrication forces of a DEM substep and its
                                  integration (Sec. 3.1.1) in one pass, the packed
                                  records alternating between two buffers; -1 default
-                                 (on), 0 off (separate passes), 1 on. Results are
+                                 (off), 0 off (separate passes), 1 on. Results are
                                  bit-identical either way; ignored where the form
                                  does not allow it (FP64 storage, fewer substeps) */
 } lbdem_tuning;

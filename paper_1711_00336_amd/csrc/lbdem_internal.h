@@ -114,7 +114,7 @@ struct Tune {
     int cell_waves;             // workgroups per CU of the streaming cell passes (moments, stream-collide):
                                 // 0 unlimited, else capped through reserved LDS; -1 default
     int fuse;                   // DEM substep forces and integration in one pass where the form
-                                // allows it (FP32 form, n_DEM >= 3): -1 default (on), 0 off, 1 on
+                                // allows it (FP32 form, n_DEM >= 3): -1 default (off), 0 off, 1 on
 };
 
 // Processing order of the DEM force pass. Slots are sorted by cell in
@@ -191,8 +191,9 @@ constexpr int64_t kDiagScratchDoubles = (int64_t)kDiagValues * kDiagMaxBlocks + 
 double *diag_scratch_on_device(int device);
 
 void launch_dem_force(const Desc &D, hipStream_t s);
-// FP32 form with n_DEM >= 3: force, torque and the integration of a substep
-// in one pass (records alternate between pk and pk2 by substep parity)
+// FP32 form with n_DEM >= 3 when asked for (tuning): force, torque and the
+// integration of a substep in one pass (records alternate between pk and pk2
+// by substep parity)
 bool dem_substep_fused(const Desc &D);
 void launch_dem_substep_fused(const Desc &D, int sub, int last, hipStream_t s);
 void launch_dem_order(const Desc &D, hipStream_t s);   // blocked processing order of the current slots

@@ -2408,7 +2408,7 @@ void launch_dem_force(const Desc &D, hipStream_t s)
         else hipLaunchKernelGGL((k_dem_force<double, false, false, false>), g, b, 0, s, D, 0, 0);
     }
 }
-bool dem_substep_fused(const Desc &D) { return D.pt.pk && use_nslot(D) && D.t.fuse != 0; }
+bool dem_substep_fused(const Desc &D) { return D.pt.pk && use_nslot(D) && D.t.fuse == 1; }
 void launch_dem_substep_fused(const Desc &D, int sub, int last, hipStream_t s)
 {
     if (D.pt.np == 0) return;
