@@ -1444,12 +1444,10 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
 // reordering that closed the last subcycle (and any rebuild), for the n_DEM
 // force passes, which then read each neighbour's record without that
 // dependent load (only with n_DEM >= kNslotMinSubsteps substeps, where that
-// saves more than the lookup pass costs). A workgroup takes kNslotRows list
-// rows, one contiguous run
-// of entries (rows are contiguous by label), and its threads take
-// consecutive entries, so the list reads and slot writes are coalesced; each
-// thread steps its (row, entry) position instead of dividing.
-constexpr int kNslotRows = 64;
+// saves more than the lookup pass costs). A thread takes four consecutive
+// entries of one row: rows hold nbr entries, a multiple of four, so each
+// quad is one aligned 16-byte load and store; quads past the row's length
+// are skipped and the tail of the last one is written as -1.
 constexpr int kNslotMinSubsteps = 3;
 __host__ __device__ __forceinline__ bool use_nslot(const Desc &D) { return D.p.n_dem >= kNslotMinSubsteps; }
 
@@ -1457,22 +1455,21 @@ __global__ __launch_bounds__(kBlock) void k_nslot(Desc D)
 {
     const Parts &P = D.pt;
     if (halted(D)) return;
-    const int64_t r0 = (int64_t)blockIdx.x * kNslotRows;
-    const int nrow = (int)min((int64_t)kNslotRows, (int64_t)P.np - r0);
-    const int nbr = P.nbr;
-    const int total = nrow * nbr;
-    const int64_t base = r0 * nbr;
-    const int dr = kBlock / nbr, dt = kBlock - dr * nbr;
-    int row = (int)threadIdx.x / nbr, t = (int)threadIdx.x - row * nbr;
-    for (int e = threadIdx.x; e < total; e += kBlock) {
-        if (t < P.nnb[r0 + row]) P.nslot[base + e] = P.slot_of[P.nlist[base + e]];
-        row += dr;
-        t += dt;
-        if (t >= nbr) {
-            t -= nbr;
-            ++row;
-        }
-    }
+    const uint32_t q4 = (uint32_t)P.nbr >> 2;
+    const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= (uint64_t)P.np * q4) return;
+    const uint64_t row = g / q4;
+    const int t = (int)(g - row * q4) * 4;
+    const int n = P.nnb[row];
+    if (t >= n) return;
+    const int64_t e = (int64_t)row * P.nbr + t;
+    const int4 lab = *reinterpret_cast<const int4 *>(P.nlist + e);
+    int4 out;
+    out.x = P.slot_of[lab.x];
+    out.y = t + 1 < n ? P.slot_of[lab.y] : -1;
+    out.z = t + 2 < n ? P.slot_of[lab.z] : -1;
+    out.w = t + 3 < n ? P.slot_of[lab.w] : -1;
+    *reinterpret_cast<int4 *>(P.nslot + e) = out;
 }
 
 // One semi-implicit Euler substep of particle i (R5: u and omega first,
@@ -1542,7 +1539,7 @@ __device__ __forceinline__ void integrate_particle(const Desc &D, int64_t i, int
 // only. Contacts are a small share of the pairs, and evaluated inline the
 // whole wavefront would step through the contact code for almost every
 // entry, since some lane nearly always has an overlap there. In the first
-// pass entries are taken two at a time, their indices, slots and particle
+// pass entries are taken three at a time, their indices, slots and particle
 // data requested together so that the memory latencies overlap. With
 // NSLOT the neighbours' current slots come from the subcycle's refreshed
 // copy of the list (k_nslot), saving a dependent load per neighbour;
@@ -1572,7 +1569,7 @@ __global__ __launch_bounds__(kBlock) void k_dem_force(Desc D, int last, int odd)
     const int n = P.nnb[me];
     // the neighbours' slots (NSLOT) or labels, in list order
     const int *S = (NSLOT ? P.nslot : P.nlist) + (int64_t)me * P.nbr;
-    constexpr int kChunk = 2;
+    constexpr int kChunk = 3;
     for (int s0 = 0; s0 < n; s0 += 64) {
         const int s1 = min(n, s0 + 64);
         uint64_t touch = 0;
@@ -2428,7 +2425,8 @@ void launch_nlist(const Desc &D, hipStream_t s)
     if (D.pt.np <= 0) return;
     hipLaunchKernelGGL(k_nlist, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
     if (use_nslot(D))
-        hipLaunchKernelGGL(k_nslot, dim3((unsigned)((D.pt.np + kNslotRows - 1) / kNslotRows)), dim3(kBlock), 0, s, D);
+        hipLaunchKernelGGL(k_nslot, dim3((unsigned)(((uint64_t)D.pt.np * (D.pt.nbr >> 2) + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, s, D);
 }
 void launch_integrate(const Desc &D, int last, hipStream_t s)
 {
