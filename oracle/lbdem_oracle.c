@@ -877,12 +877,12 @@ void orc_diagnostics(const orc_params *p, const orc_state *s, orc_diag *out)
  *       (b) u_f and, with lift on, curl u_f (grad P depends on rho only
  *           and is evaluated once per step)
  *       (c) F_l (lift on) and F_am per particle, distributed to f_ext
- *       (d) re-evaluate u_f with the updated f_ext
+ *       (d) u_f once more, now including the spread forces of (c)
  *       (e) F_pr, F_d per particle, F_d distributed; F_g (+ buoyancy)
  *       (f) accumulate f_ext / n_int for the LBM step
  *       (g) n_DEM DEM substeps with the fluid forces frozen
  *       (h) du_p/dt over the subcycle, for the next added-mass evaluation
- *       (i) re-evaluate eps_f
+ *       (i) eps_f at the new particle positions
  *   S3  GNS-LBM collide + stream with eps_f and the averaged force density.
  *
  * Readings (the paper does not fix these; parity unpinned against it):
@@ -1027,7 +1027,7 @@ int orc_step(const orc_params *pin, orc_state *s, orc_aux *aux)
             spread(p, &st[i], fext, 3, F1, -1.0);
         }
 
-        /* (d) re-evaluate u_f = (j + f_ext/2) / (rho eps_f) */
+        /* (d) u_f = (j + f_ext/2) / (rho eps_f), f_ext now holding the spread forces */
         for (int64_t c = 0; c < nc; ++c) {
             for (int a = 0; a < 3; ++a) uf[a * nc + c] = (j[a * nc + c] + 0.5 * fext[a * nc + c]) / (rho[c] * eps[c]);
             epsp[c] = 1.0 - eps[c];
