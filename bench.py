@@ -544,6 +544,21 @@ def run_step_workload(lbdem, torch, case, wl_name, K, W, ksteps, stream, args):
                 nlist=nlist, nreach=nreach, tuning=dict(tuning, dem_order_resolved=dem_order, fused=fused))
 
 
+def calibration_copies(torch, mib):
+    """A plain device copy of known size (5 times), for scaling the HBM byte
+    counters of a profiled run (FETCH_SIZE and WRITE_SIZE per dispatch)."""
+    if mib <= 0:
+        return
+    nb = mib << 20
+    src_t = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+    dst_t = torch.empty_like(src_t)
+    for _ in range(5):
+        dst_t.copy_(src_t)
+    torch.cuda.synchronize()
+    print(f"[bench] calibration copies: 5 x {nb} bytes read and written", file=sys.stderr, flush=True)
+    del src_t, dst_t
+
+
 def richardson_zaki(eps, re_t):
     """<u_pS>/u_pT = (1 - <eps_p>)^kappa with Richardson and Zaki's kappa(Re_T)
     (Sec. 4, Eqs. hinderedSettlingCorrelation, hinderedCoefficientRZ)."""
@@ -738,8 +753,9 @@ def main():
         import torch
         from paper_1711_00336_amd import lbdem
         torch.cuda.init()
-        print(json.dumps({"mode": "k10", "roofline_stream_collide": k10_roofline(lbdem, torch.cuda.current_stream(),
-                                                                                 visc=args.visc)}), flush=True)
+        roof = k10_roofline(lbdem, torch.cuda.current_stream(), visc=args.visc)
+        calibration_copies(torch, args.calib_copy_mib)
+        print(json.dumps({"mode": "k10", "roofline_stream_collide": roof}), flush=True)
         return
 
     import torch
@@ -772,16 +788,7 @@ def main():
                 "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in r2["times"].items()},
                 "u_ps": r2["diag"]["u_ps"]}
 
-    if args.calib_copy_mib > 0:
-        # a plain device copy of known size, for scaling the HBM byte counters
-        nb = args.calib_copy_mib << 20
-        src_t = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
-        dst_t = torch.empty_like(src_t)
-        for _ in range(5):
-            dst_t.copy_(src_t)
-        torch.cuda.synchronize()
-        print(f"[bench] calibration copies: 5 x {nb} bytes read and written", file=sys.stderr, flush=True)
-        del src_t, dst_t
+    calibration_copies(torch, args.calib_copy_mib)
 
     cpu = None
     if not args.no_cpu_baseline:
