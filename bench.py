@@ -84,6 +84,10 @@ def workload(name, seed, cache=None):
         return I.Case(f"dense-256x256x512-eps0.4", p, parts, seed)
     if name == "dilute":
         return I.case_dilute_periodic(seed, n=128, eps_p=0.05, d=0.8, precision="fp32dev")
+    if name == "dense128":
+        # the dense packing on an eighth of the grid (128 x 128 x 256 cells,
+        # ~3.2 M spheres): the same kernels at a size that profiles quickly
+        return I.case_dense_walled(seed, n=(128, 128, 256), eps_p=0.4, precision="fp32dev")
     if name == "dilute64":
         return I.case_dilute_periodic(seed, n=128, eps_p=0.05, d=0.8, precision="fp64")
     if name == "small":
@@ -704,7 +708,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="dense", help="dense (headline) | dilute | dilute64 | small")
+    ap.add_argument("--workload", default="dense", help="dense (headline) | dense128 | dilute | dilute64 | small")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--pack-cache", default=None,
                     help="npz file that keeps the dense packing between runs of one session")
