@@ -1444,32 +1444,35 @@ __global__ __launch_bounds__(kBlock) void k_nlist(Desc D)
 // reordering that closed the last subcycle (and any rebuild), for the n_DEM
 // force passes, which then read each neighbour's record without that
 // dependent load (only with n_DEM >= kNslotMinSubsteps substeps, where that
-// saves more than the lookup pass costs). A thread takes four consecutive
-// entries of one row: rows hold nbr entries, a multiple of four, so each
-// quad is one aligned 16-byte load and store; quads past the row's length
-// are skipped and the tail of the last one is written as -1.
+// saves more than the lookup pass costs). kNslotLanes lanes share a row and
+// take its entries four at a time (rows hold nbr entries, a multiple of
+// four, so each quad is one aligned 16-byte load and store), up to the
+// row's length only: the capacity is about three times the mean length,
+// and a thread per quad of the whole capacity would mostly find nothing to
+// do. The tail of a row's last quad is written as -1.
 constexpr int kNslotMinSubsteps = 3;
 __host__ __device__ __forceinline__ bool use_nslot(const Desc &D) { return D.p.n_dem >= kNslotMinSubsteps; }
+constexpr int kNslotLanes = 8;
 
 __global__ __launch_bounds__(kBlock) void k_nslot(Desc D)
 {
     const Parts &P = D.pt;
     if (halted(D)) return;
-    const uint32_t q4 = (uint32_t)P.nbr >> 2;
     const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= (uint64_t)P.np * q4) return;
-    const uint64_t row = g / q4;
-    const int t = (int)(g - row * q4) * 4;
+    const uint64_t row = g / kNslotLanes;
+    if (row >= (uint64_t)P.np) return;
+    const int lane = (int)(g % kNslotLanes);
     const int n = P.nnb[row];
-    if (t >= n) return;
-    const int64_t e = (int64_t)row * P.nbr + t;
-    const int4 lab = *reinterpret_cast<const int4 *>(P.nlist + e);
-    int4 out;
-    out.x = P.slot_of[lab.x];
-    out.y = t + 1 < n ? P.slot_of[lab.y] : -1;
-    out.z = t + 2 < n ? P.slot_of[lab.z] : -1;
-    out.w = t + 3 < n ? P.slot_of[lab.w] : -1;
-    *reinterpret_cast<int4 *>(P.nslot + e) = out;
+    const int64_t rb = (int64_t)row * P.nbr;
+    for (int t = lane * 4; t < n; t += kNslotLanes * 4) {
+        const int4 lab = *reinterpret_cast<const int4 *>(P.nlist + rb + t);
+        int4 out;
+        out.x = P.slot_of[lab.x];
+        out.y = t + 1 < n ? P.slot_of[lab.y] : -1;
+        out.z = t + 2 < n ? P.slot_of[lab.z] : -1;
+        out.w = t + 3 < n ? P.slot_of[lab.w] : -1;
+        *reinterpret_cast<int4 *>(P.nslot + rb + t) = out;
+    }
 }
 
 // One semi-implicit Euler substep of particle i (R5: u and omega first,
@@ -2425,7 +2428,7 @@ void launch_nlist(const Desc &D, hipStream_t s)
     if (D.pt.np <= 0) return;
     hipLaunchKernelGGL(k_nlist, dim3(nblocks(D.pt.np)), dim3(kBlock), 0, s, D);
     if (use_nslot(D))
-        hipLaunchKernelGGL(k_nslot, dim3((unsigned)(((uint64_t)D.pt.np * (D.pt.nbr >> 2) + kBlock - 1) / kBlock)),
+        hipLaunchKernelGGL(k_nslot, dim3((unsigned)(((uint64_t)D.pt.np * kNslotLanes + kBlock - 1) / kBlock)),
                            dim3(kBlock), 0, s, D);
 }
 void launch_integrate(const Desc &D, int last, hipStream_t s)
