@@ -52,13 +52,19 @@ def _gen_request(args):
     return c, steps
 
 
+def _pool_init():
+    from paper_1711_00336_amd import inputs as I
+    I.set_relax_threads(1)
+
+
 def _pool_map(fn, items, what):
-    """Generate inputs on the host in a process pool (CPU share: at most 16)."""
+    """Generate inputs on the host in a process pool (CPU share: at most 16),
+    one OpenMP thread per worker."""
     import concurrent.futures as cf
     workers = max(1, min(16, os.cpu_count() or 1, len(items)))
     out = [None] * len(items)
     t0 = time.perf_counter()
-    with cf.ProcessPoolExecutor(workers) as ex:
+    with cf.ProcessPoolExecutor(workers, initializer=_pool_init) as ex:
         futs = {ex.submit(fn, it): k for k, it in enumerate(items)}
         done = 0
         for f in cf.as_completed(futs):

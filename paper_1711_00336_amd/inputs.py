@@ -228,6 +228,16 @@ def _neighbour_pairs(pos, box, periodic, cell, cutoff):
 _RELAX_SRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "inputs_relax.c")
 _RELAX_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libinputs_relax.so")
 _relax_fn = None
+# OpenMP threads of the overlap removal: 0 = the OpenMP default (all
+# cores); processes that generate inputs side by side set 1, since many
+# processes each spinning up all cores' threads mostly wait at barriers.
+# The packing does not depend on it.
+_relax_threads = 0
+
+
+def set_relax_threads(n: int) -> None:
+    global _relax_threads
+    _relax_threads = max(0, int(n))
 
 
 def build_relax(force: bool = False) -> str:
@@ -249,7 +259,8 @@ def _relax_lib():
         f = lib.lbdem_inputs_relax
         f.restype = ctypes.c_int
         dp = ctypes.POINTER(ctypes.c_double)
-        f.argtypes = [ctypes.c_int64, dp, dp, dp, ctypes.POINTER(ctypes.c_int32), ctypes.c_double, ctypes.c_int32]
+        f.argtypes = [ctypes.c_int64, dp, dp, dp, ctypes.POINTER(ctypes.c_int32), ctypes.c_double, ctypes.c_int32,
+                      ctypes.c_int32]
         _relax_fn = f
     return _relax_fn
 
@@ -270,7 +281,7 @@ def _relax(pos, r, box, periodic, tol, max_it=4000, progress=None):
     while done < max_it:
         k = min(chunk, max_it - done)
         it = _relax_lib()(len(r), pos.ctypes.data_as(dp), r.ctypes.data_as(dp), boxa.ctypes.data_as(dp),
-                          per.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(tol), int(k))
+                          per.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(tol), int(k), _relax_threads)
         if it >= 0:
             return pos, True
         done += k

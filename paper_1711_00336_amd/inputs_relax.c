@@ -103,11 +103,16 @@ static void relax_cell(int64_t c, int cx, int cy, int cz, const int nb[3], const
     *maxov_out = maxov;
 }
 
-/* returns the number of sweeps used, or -1 if max_sweeps was reached */
+/* returns the number of sweeps used, or -1 if max_sweeps was reached;
+ * nthreads > 0 sets the OpenMP thread count (the result does not depend on
+ * it), 0 keeps the default */
 int lbdem_inputs_relax(int64_t n, double *pos, const double *r, const double *box, const int32_t *per,
-                       double tol, int32_t max_sweeps)
+                       double tol, int32_t max_sweeps, int32_t nthreads)
 {
     if (n <= 1) return 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
     double rmax = 0.0;
     for (int64_t i = 0; i < n; ++i) rmax = fmax(rmax, r[i]);
     int nb[3];

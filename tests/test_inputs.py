@@ -47,3 +47,18 @@ def test_dense_polydisperse_relaxed():
     if len(I_):
         ov = 0.5 * (p.d[I_] + p.d[J]) - np.sqrt((dv ** 2).sum(1))
         assert ov.max() < 1e-3 * p.d.min()
+
+
+def test_dense_packing_does_not_depend_on_the_thread_count():
+    """The overlap removal visits cells in 27 colour classes whose
+    neighbourhoods are disjoint, so its result is the same with one OpenMP
+    thread (as in the parallel input generators) and with several."""
+    from paper_1711_00336_amd import inputs as I
+    try:
+        I.set_relax_threads(1)
+        a = I.case_dense_walled(3, n=(24, 24, 32), eps_p=0.4, precision="fp64").particles.x
+        I.set_relax_threads(4)
+        b = I.case_dense_walled(3, n=(24, 24, 32), eps_p=0.4, precision="fp64").particles.x
+    finally:
+        I.set_relax_threads(0)
+    assert np.array_equal(a, b)
