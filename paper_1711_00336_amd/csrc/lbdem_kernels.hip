@@ -1344,12 +1344,6 @@ template <typename T> __device__ __forceinline__ void load_rec(const DemRec *pk,
     }
 }
 
-template <typename T, bool REC> __device__ __forceinline__ void load_particle(const Parts &P, int64_t i, PV<T> &v)
-{
-    if constexpr (REC) load_rec(P.pk, i, v);
-    else load_pv(P, i, v);
-}
-
 // Once a step has flagged instability (non-finite or runaway particles),
 // the domain's state is no longer meaningful and is reported at the next
 // sync. The binning and neighbour-search kernels then do nothing: positions
